@@ -1,0 +1,217 @@
+/*
+ * hrrm.h - C ABI of the MI355X (gfx950) hierarchical recursive running median.
+ *
+ * The operation is the running median (and, more generally, the running k-th
+ * order statistic) of Alekseychuk, "Hierarchical Recursive Running Median":
+ * for every pixel p of a 2-D image (or voxel of a 3-D volume) the output is the
+ * K-th smallest (0-based) of the N = (2r+1)^D input values in the window
+ * centred on p (Sec. II, definition of the median; Sec. III, the
+ * get_order_statistic procedure and its percentile K).  The median is
+ * K = (N-1)/2; N is always odd.  Borders are clamp-to-edge: window positions
+ * outside the image take the nearest edge pixel, with multiplicity, so every
+ * window holds exactly N values.
+ *
+ * The result is computed with the paper's method - per-column interval-
+ * occurrence trees (Sec. III, Sec. III-A, Sec. III-B) updated recursively as the
+ * window moves down one row, window counts built on demand from the column
+ * trees, and a descent through the tree one level at a time - in hand-written
+ * HIP kernels.  The output is bit-identical to any correct median filter.
+ *
+ * Conventions shared by every entry point:
+ *  - Pixel buffers are DEVICE pointers (hipMalloc / torch CUDA tensors), owned
+ *    by the caller.  The library keeps no pointer after the enqueued work ends.
+ *  - Strides are in ELEMENTS (as torch.Tensor.stride()); x is fastest.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = default stream)
+ *    and is asynchronous: calls never synchronise the host.
+ *  - Arguments are validated on the host before anything is enqueued; a
+ *    rejected call enqueues nothing.  Errors are returned as negative status
+ *    codes, with a message in hrrm_last_error() (thread-local).  Calls never
+ *    throw across the ABI and never abort.
+ *  - A zero-sized image is a successful no-op.  r >= image size is valid.
+ *  - src and dst must not overlap.
+ */
+#ifndef HRRM_H
+#define HRRM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define HRRM_OK 0
+#define HRRM_EINVAL (-1)       /* bad argument (null pointer, bad size, overlap ...) */
+#define HRRM_ENOMEM (-2)       /* device memory for a workspace could not be obtained */
+#define HRRM_EUNSUPPORTED (-3) /* valid request outside what this build supports */
+#define HRRM_EDEVICE (-4)      /* a HIP runtime call failed */
+#define HRRM_EAGAIN (-5)       /* try again later (serving queue full / not finished) */
+
+typedef enum { HRRM_U8 = 1, HRRM_U16 = 2 } hrrm_dtype;
+
+/* Tree topology.  PLAIN: the uniform interval-occurrences tree (Sec. III), each
+ * split halves its interval, height = bit depth.  ADAPTIVE: the adaptive tree
+ * of Sec. III-C, split so that both children are visited about equally often,
+ * estimated from the 1:1 mix of the input's global histogram and the global
+ * histogram of its running (box) mean; frequent grey values get short paths.
+ * Both give identical output. */
+typedef enum { HRRM_PLAIN = 0, HRRM_ADAPTIVE = 1 } hrrm_variant;
+
+/* Largest supported radius.  2-D: column counts are bytes (<= 2r+1 <= 255).
+ * 3-D: a column holds (2r+1)^2 values, also kept in a byte. */
+#define HRRM_MAX_R_2D 127
+#define HRRM_MAX_R_3D 7
+
+typedef struct hrrm_ctx_s* hrrm_ctx;
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char* hrrm_last_error(void);
+
+/* Library version string. */
+const char* hrrm_version(void);
+
+/* Create a context bound to HIP device `device`.  The context owns device
+ * workspaces (adaptive-topology histograms and tables) and the tile
+ * configuration table; it is not thread-safe (one context per host thread, or
+ * external locking).  *out receives the handle. */
+int hrrm_ctx_create(int device, hrrm_ctx* out);
+
+/* Destroy a context and free its workspaces.  The caller must make sure no
+ * enqueued work of this context is still running.  NULL is a no-op. */
+int hrrm_ctx_destroy(hrrm_ctx ctx);
+
+/* Pre-size the workspaces so later calls up to these sizes allocate nothing
+ * (required before capturing calls into a HIP graph).  max_pixels counts
+ * pixels (2-D) or voxels (3-D). */
+int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t max_r,
+                     hrrm_variant variant);
+
+/* Running median over (2r+1) x (2r+1) windows (Sec. III).
+ *   d_src, d_dst : device buffers of `dtype` elements; row y of the image
+ *                  starts at element y * src_row_stride (dst_row_stride).
+ *   width, height: image size in pixels (>= 0).
+ *   r            : radius, 0 <= r <= HRRM_MAX_R_2D (window 2r+1).
+ * Errors: EINVAL (null pointer with non-zero size, negative size or r,
+ * stride < width, misaligned u16 pointer, overlapping buffers, unknown dtype or
+ * variant), EUNSUPPORTED (r > HRRM_MAX_R_2D), ENOMEM, EDEVICE. */
+int hrrm_median2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
+                  int64_t height, int64_t src_row_stride, int64_t dst_row_stride, int32_t r,
+                  hrrm_variant variant, void* hip_stream);
+
+/* Running median over (2r+1)^3 cubes of a volume (Sec. III, closing remark on
+ * the N-dimensional extension).  Element (x, y, z) is at
+ * z * slice_stride + y * row_stride + x.  0 <= r <= HRRM_MAX_R_3D.
+ * Errors as hrrm_median2d, plus EINVAL if a slice stride is smaller than
+ * row_stride * height. */
+int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
+                  int64_t height, int64_t depth, int64_t src_row_stride, int64_t src_slice_stride,
+                  int64_t dst_row_stride, int64_t dst_slice_stride, int32_t r,
+                  hrrm_variant variant, void* hip_stream);
+
+/* Running k-th order statistic, 0 <= rank < (2r+1)^2 (Sec. III,
+ * get_order_statistic with K = rank; Sec. VI, "other order statistics").
+ * rank = 0 is the running minimum, (2r+1)^2-1 the running maximum.
+ * drop_levels (PLAIN only, 0..bit depth) stops the descent that many levels
+ * above the leaves and returns the lower bound of the last node reached
+ * (Sec. III-D, variable precision): the exact result with its drop_levels low
+ * bits cleared, error < 2^drop_levels grey values.  ADAPTIVE requires
+ * drop_levels == 0 (its nodes are not aligned blocks). */
+int hrrm_rank2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
+                int64_t height, int64_t src_row_stride, int64_t dst_row_stride, int32_t r,
+                int64_t rank, int32_t drop_levels, hrrm_variant variant, void* hip_stream);
+
+/* ---- Batched launch (many uneven images in one persistent kernel) --------- */
+
+/* One image of a batch.  Pointers are device pointers; strides in elements. */
+typedef struct {
+  const void* src;
+  void* dst;
+  int64_t width, height;
+  int64_t src_row_stride, dst_row_stride;
+  int32_t dtype; /* hrrm_dtype */
+  int32_t r;
+} hrrm_image;
+
+/* Filter `count` independent 2-D images (PLAIN median) in ONE persistent
+ * launch: workgroups pull tiles of all images from a device work counter, with
+ * the tile shape of each image taken from the context's tile table (see
+ * hrrm_autotune).  `images` is a HOST array; it is copied into a device
+ * descriptor ring owned by the context.  The launch is captured once per
+ * (context, stream) into a HIP graph and replayed for later batches.
+ * Errors: as hrrm_median2d for any image; EINVAL if count < 0 or
+ * count > hrrm_batch_capacity(). */
+int hrrm_median2d_batched(hrrm_ctx ctx, const hrrm_image* images, int32_t count,
+                          void* hip_stream);
+
+/* Largest `count` hrrm_median2d_batched accepts. */
+int32_t hrrm_batch_capacity(void);
+
+/* ---- Tile configuration / autotuning ------------------------------------- */
+
+/* Time the tile candidates for (dtype, r, variant) on a synthetic image of
+ * width x height drawn on the device, keep the fastest in the context's tile
+ * table, and return its index in *best (may be NULL).  Synchronises the
+ * context's device.  If cache_path is not NULL the table is also written there
+ * (JSON).  hrrm_load_tuning reads such a file back. */
+int hrrm_autotune(hrrm_ctx ctx, hrrm_dtype dtype, int32_t r, hrrm_variant variant,
+                  int64_t width, int64_t height, const char* cache_path, int32_t* best);
+int hrrm_load_tuning(hrrm_ctx ctx, const char* cache_path);
+
+/* ---- Serving: continuous-batching request loop ---------------------------- */
+
+typedef struct hrrm_server_s* hrrm_server;
+
+typedef struct {
+  const void* src;        /* HOST pointer to the input (copied on admission) */
+  int64_t width, height;  /* pixels */
+  int64_t src_row_stride; /* elements */
+  int32_t dtype;          /* hrrm_dtype */
+  int32_t r;
+} hrrm_request;
+
+typedef struct {
+  void* d_dst;            /* device buffer with the output (row stride = width), owned by
+                             the server until hrrm_server_release */
+  int64_t width, height;
+  int32_t dtype;
+  int32_t status;         /* HRRM_OK, or the error that failed the request */
+  double t_submit;        /* seconds on the server clock */
+  double t_admit;
+  double t_done;
+} hrrm_result;
+
+/* Start a server on the context's device.  device_mem_budget bounds the bytes
+ * of device memory held by admitted requests (input + output); max_inflight
+ * bounds the number of admitted, unreleased requests; max_queue bounds the
+ * host queue of not-yet-admitted requests. */
+int hrrm_server_create(hrrm_ctx ctx, size_t device_mem_budget, int32_t max_inflight,
+                       int32_t max_queue, hrrm_server* out);
+
+/* Queue a request (non-blocking; the input is read on admission, so it must
+ * stay valid until hrrm_server_poll reports the ticket done).  EAGAIN if the
+ * queue is full, EINVAL for a malformed request, ENOMEM if it can never fit the
+ * memory budget. */
+int hrrm_server_submit(hrrm_server srv, const hrrm_request* req, uint64_t* ticket);
+
+/* HRRM_OK with *res filled once the ticket is done; EAGAIN before. */
+int hrrm_server_poll(hrrm_server srv, uint64_t ticket, hrrm_result* res);
+
+/* Give the output buffer of a done ticket back to the server. */
+int hrrm_server_release(hrrm_server srv, uint64_t ticket);
+
+/* Cancel a queued (not yet admitted) request: OK if cancelled, EAGAIN if it
+ * was already admitted. */
+int hrrm_server_cancel(hrrm_server srv, uint64_t ticket);
+
+/* Server clock (seconds), the clock of the t_* stamps. */
+double hrrm_server_now(hrrm_server srv);
+
+/* Stop the server (waits for admitted work) and free everything it holds. */
+int hrrm_server_destroy(hrrm_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRRM_H */

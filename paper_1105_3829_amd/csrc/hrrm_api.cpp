@@ -1,0 +1,317 @@
+// Host side of the C ABI declared in include/hrrm.h: argument validation,
+// contexts and their device workspaces, tile configuration, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hrrm.h"
+#include "hrrm_ctx.h"
+#include "hrrm_internal.h"
+
+namespace hrrm {
+
+namespace {
+thread_local std::string g_err;
+}
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+  return fail(HRRM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+const char* last_error() { return g_err.c_str(); }
+
+// ---- tile table ------------------------------------------------------------
+
+TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
+                        int64_t d) {
+  TileConfig t{};
+  t.min_group = 2;
+  t.max_groups = 64;
+  t.nslots = 0;
+  t.tiered_u8 = 0;
+  t.lds_budget = 80 * 1024;
+  // Enough workgroups to fill 256 CUs several times over, while keeping the
+  // per-segment start-up (2r+1 rows inserted per column) small against the
+  // rows a segment produces.
+  const int64_t strips = (w + kBlock - 1) / kBlock;
+  const int64_t want_wg = 2048;
+  int64_t rows = (strips * h * d) / want_wg;
+  const int64_t min_rows = std::max<int64_t>(16, 2 * (2 * r + 1));
+  rows = std::max<int64_t>(rows, min_rows);
+  rows = std::min<int64_t>(rows, 512);
+  t.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(rows, h));
+  (void)bytes;
+  (void)dims;
+  (void)adaptive;
+  return t;
+}
+
+TileConfig Context::tile_for(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
+                             int64_t d) const {
+  TileConfig t = default_tile(bytes, dims, r, adaptive, w, h, d);
+  for (const auto& e : tuned) {
+    if (e.bytes == bytes && e.dims == dims && e.r == r && e.adaptive == (int)adaptive) {
+      TileConfig u = e.cfg;
+      // a tuned segment height is a target; never exceed the image
+      u.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(u.seg_rows, h));
+      return u;
+    }
+  }
+  return t;
+}
+
+// ---- validation --------------------------------------------------------------
+
+static bool overlap(const void* a, size_t an, const void* b, size_t bn) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bn && pb < pa + an;
+}
+
+int validate(const void* src, const void* dst, int dtype, int64_t w, int64_t h, int64_t d,
+             int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r, int dims) {
+  if (dtype != HRRM_U8 && dtype != HRRM_U16) return fail(HRRM_EINVAL, "unknown dtype %d", dtype);
+  if (w < 0 || h < 0 || d < 0) return fail(HRRM_EINVAL, "negative image size");
+  if (r < 0) return fail(HRRM_EINVAL, "negative radius %d", r);
+  const int maxr = dims == 2 ? HRRM_MAX_R_2D : HRRM_MAX_R_3D;
+  if (r > maxr)
+    return fail(HRRM_EUNSUPPORTED, "radius %d above the supported maximum %d for %d-D", r, maxr,
+                dims);
+  if (w == 0 || h == 0 || d == 0) return HRRM_OK;
+  if (!src || !dst) return fail(HRRM_EINVAL, "null image pointer");
+  if (srs < w || drs < w) return fail(HRRM_EINVAL, "row stride smaller than width");
+  if (dims == 3 && (sss < srs * h || dss < drs * h))
+    return fail(HRRM_EINVAL, "slice stride smaller than row_stride * height");
+  const int bytes = dtype == HRRM_U8 ? 1 : 2;
+  if (bytes == 2 && ((((uintptr_t)src) | ((uintptr_t)dst)) & 1))
+    return fail(HRRM_EINVAL, "uint16 buffer not 2-byte aligned");
+  const int64_t limit = (int64_t)1 << 40;
+  if (w > limit || h > limit || d > limit || srs > limit || drs > limit)
+    return fail(HRRM_EINVAL, "image dimensions out of range");
+  const size_t sbytes =
+      (size_t)bytes * (size_t)(dims == 3 ? (d - 1) * sss + (h - 1) * srs + w : (h - 1) * srs + w);
+  const size_t dbytes =
+      (size_t)bytes * (size_t)(dims == 3 ? (d - 1) * dss + (h - 1) * drs + w : (h - 1) * drs + w);
+  if (overlap(src, sbytes, dst, dbytes)) return fail(HRRM_EINVAL, "src and dst overlap");
+  return HRRM_OK;
+}
+
+// ---- launch ------------------------------------------------------------------
+
+int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
+               int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,
+               int64_t rank, int drop, int variant, int dims, hipStream_t stream,
+               const TileConfig* force) {
+  const int bytes = dtype == HRRM_U8 ? 1 : 2;
+  const int bits = 8 * bytes;
+  const bool adaptive = variant == HRRM_ADAPTIVE;
+  TileConfig t = force ? *force : ctx->tile_for(bytes, dims, r, adaptive, w, h, d);
+  if (t.seg_rows <= 0) t.seg_rows = 1;
+  t.seg_rows = (int32_t)std::min<int64_t>(t.seg_rows, h);
+  const bool tiered = bytes == 2 || t.tiered_u8 != 0;
+
+  MedianArgs a{};
+  a.src = src;
+  a.dst = dst;
+  a.w = w;
+  a.h = h;
+  a.d = dims == 3 ? d : 1;
+  a.srs = srs;
+  a.sss = dims == 3 ? sss : 0;
+  a.drs = drs;
+  a.dss = dims == 3 ? dss : 0;
+  a.rank = rank;
+  a.r = r;
+  a.bits = bits;
+  a.stop = adaptive ? 1 << 30 : bits - drop;
+  a.seg_rows = t.seg_rows;
+  a.strips = (int32_t)((w + kBlock - 1) / kBlock);
+  a.segs = (int32_t)((h + t.seg_rows - 1) / t.seg_rows);
+  a.ncols = kBlock + 2 * r + 1;
+  a.cp = (a.ncols + 3) & ~3;
+  a.min_group = std::max(1, t.min_group);
+  a.max_groups = std::max(0, t.max_groups);
+  a.topo = nullptr;
+
+  const int64_t grid = (int64_t)a.strips * a.segs * a.d;
+  if (grid > 0x7fffffff) return fail(HRRM_EUNSUPPORTED, "image too large for one launch");
+
+  if (tiered) {
+    const size_t meta = median_lds_bytes(bytes, adaptive, true, a.ncols, a.cp, 0);
+    const size_t slot_bytes = (size_t)kTierNodes * a.cp;
+    const size_t budget = (size_t)std::min(std::max(t.lds_budget, 16 * 1024), kLdsLimit);
+    int fit = budget > meta ? (int)((budget - meta) / slot_bytes) : 0;
+    int ns = t.nslots > 0 ? t.nslots : fit;
+    ns = std::min(ns, std::max(fit, 1));
+    ns = std::min(ns, kMaxSlots);
+    if (ns < 1) ns = 1;
+    a.nslots = ns;
+  } else {
+    a.nslots = 1;
+  }
+  const size_t lds = median_lds_bytes(bytes, adaptive, tiered, a.ncols, a.cp, a.nslots);
+  if (lds > (size_t)kLdsLimit)
+    return fail(HRRM_EUNSUPPORTED, "radius %d needs %zu bytes of LDS per workgroup", r, lds);
+
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  if (adaptive) {
+    int rc = ctx->ensure_topology(bytes, w * h * a.d);
+    if (rc != HRRM_OK) return rc;
+    a.topo = (const TopoNode*)ctx->topo;
+    e = launch_topology(a, bytes, dims, ctx->topo_ws, (TopoNode*)ctx->topo, stream);
+    if (e != hipSuccess) return fail_hip(e, "adaptive topology launch");
+  }
+  e = launch_median(a, bytes, dims, adaptive, tiered, stream);
+  if (e != hipSuccess) return fail_hip(e, "median kernel launch");
+  return HRRM_OK;
+}
+
+// ---- context -----------------------------------------------------------------
+
+int Context::ensure_topology(int bytes, int64_t pixels) {
+  const int bits = 8 * bytes;
+  const size_t need_ws = topology_workspace_bytes(bits, pixels);
+  const size_t need_topo = sizeof(TopoNode) << bits;  // nodes + root entry
+  if (need_ws > topo_ws_bytes) {
+    if (capture_locked) return fail(HRRM_ENOMEM, "workspace too small (reserve before capture)");
+    if (topo_ws) (void)hipFree(topo_ws);
+    topo_ws = nullptr;
+    topo_ws_bytes = 0;
+    hipError_t e = hipMalloc(&topo_ws, need_ws);
+    if (e != hipSuccess) return fail(HRRM_ENOMEM, "topology workspace: %s", hipGetErrorString(e));
+    topo_ws_bytes = need_ws;
+  }
+  if (need_topo > topo_bytes) {
+    if (capture_locked) return fail(HRRM_ENOMEM, "workspace too small (reserve before capture)");
+    if (topo) (void)hipFree(topo);
+    topo = nullptr;
+    topo_bytes = 0;
+    hipError_t e = hipMalloc(&topo, need_topo);
+    if (e != hipSuccess) return fail(HRRM_ENOMEM, "topology table: %s", hipGetErrorString(e));
+    topo_bytes = need_topo;
+  }
+  return HRRM_OK;
+}
+
+Context::~Context() {
+  (void)hipSetDevice(device);
+  if (topo_ws) (void)hipFree(topo_ws);
+  if (topo) (void)hipFree(topo);
+  release_batch();
+}
+
+}  // namespace hrrm
+
+using namespace hrrm;
+
+extern "C" {
+
+const char* hrrm_last_error(void) { return last_error(); }
+
+const char* hrrm_version(void) { return "hrrm-mi355x 0.1 (gfx950)"; }
+
+int hrrm_ctx_create(int device, hrrm_ctx* out) {
+  clear_error();
+  if (!out) return fail(HRRM_EINVAL, "null output handle");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return fail_hip(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(HRRM_EINVAL, "device %d out of range (%d)", device, n);
+  Context* c = new (std::nothrow) Context();
+  if (!c) return fail(HRRM_ENOMEM, "out of host memory");
+  c->device = device;
+  *out = reinterpret_cast<hrrm_ctx>(c);
+  return HRRM_OK;
+}
+
+int hrrm_ctx_destroy(hrrm_ctx ctx) {
+  clear_error();
+  delete reinterpret_cast<Context*>(ctx);
+  return HRRM_OK;
+}
+
+int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t max_r,
+                     hrrm_variant variant) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  if (dtype != HRRM_U8 && dtype != HRRM_U16) return fail(HRRM_EINVAL, "unknown dtype");
+  if (max_pixels < 0 || max_r < 0) return fail(HRRM_EINVAL, "negative size");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  if (variant == HRRM_ADAPTIVE) return c->ensure_topology(dtype == HRRM_U8 ? 1 : 2, max_pixels);
+  return HRRM_OK;
+}
+
+int hrrm_median2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
+                  int64_t height, int64_t src_row_stride, int64_t dst_row_stride, int32_t r,
+                  hrrm_variant variant, void* hip_stream) {
+  return hrrm_rank2d(ctx, d_src, d_dst, dtype, width, height, src_row_stride, dst_row_stride, r,
+                     ((int64_t)(2 * r + 1) * (2 * r + 1) - 1) / 2, 0, variant, hip_stream);
+}
+
+int hrrm_rank2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
+                int64_t height, int64_t src_row_stride, int64_t dst_row_stride, int32_t r,
+                int64_t rank, int32_t drop_levels, hrrm_variant variant, void* hip_stream) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  if (variant != HRRM_PLAIN && variant != HRRM_ADAPTIVE)
+    return fail(HRRM_EINVAL, "unknown variant %d", (int)variant);
+  int rc = validate(d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride, 0,
+                    r, 2);
+  if (rc != HRRM_OK) return rc;
+  const int64_t n = (int64_t)(2 * r + 1) * (2 * r + 1);
+  if (rank < 0 || rank >= n) return fail(HRRM_EINVAL, "rank %lld outside 0..%lld", (long long)rank,
+                                         (long long)(n - 1));
+  const int bits = dtype == HRRM_U8 ? 8 : 16;
+  if (drop_levels < 0 || drop_levels > bits)
+    return fail(HRRM_EINVAL, "drop_levels %d outside 0..%d", drop_levels, bits);
+  if (drop_levels != 0 && variant == HRRM_ADAPTIVE)
+    return fail(HRRM_EINVAL, "reduced precision needs the uniform (PLAIN) tree");
+  if (width == 0 || height == 0) return HRRM_OK;
+  return run_filter(c, d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride,
+                    0, r, rank, drop_levels, variant, 2, (hipStream_t)hip_stream, nullptr);
+}
+
+int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
+                  int64_t height, int64_t depth, int64_t src_row_stride, int64_t src_slice_stride,
+                  int64_t dst_row_stride, int64_t dst_slice_stride, int32_t r,
+                  hrrm_variant variant, void* hip_stream) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  if (variant != HRRM_PLAIN && variant != HRRM_ADAPTIVE)
+    return fail(HRRM_EINVAL, "unknown variant %d", (int)variant);
+  int rc = validate(d_src, d_dst, dtype, width, height, depth, src_row_stride, src_slice_stride,
+                    dst_row_stride, dst_slice_stride, r, 3);
+  if (rc != HRRM_OK) return rc;
+  if (width == 0 || height == 0 || depth == 0) return HRRM_OK;
+  const int64_t s = 2 * r + 1;
+  return run_filter(c, d_src, d_dst, dtype, width, height, depth, src_row_stride,
+                    src_slice_stride, dst_row_stride, dst_slice_stride, r, (s * s * s - 1) / 2, 0,
+                    variant, 3, (hipStream_t)hip_stream, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Internal declarations shared by the HIP kernels and the host-side C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hrrm {
+
+constexpr int kBlock = 256;          // threads per workgroup = output columns per strip
+constexpr int kWaves = kBlock / 64;  // wave64
+constexpr int kTierLevels = 4;       // tree levels held by one tier slot
+constexpr int kTierNodes = (1 << kTierLevels) - 1;  // left-node counters per tier slot
+constexpr int kDenseNodes = 255;     // left-node counters of a full 8-bit tree
+constexpr int kHash = 128;           // slot hash-table entries (power of two)
+constexpr int kMaxSlots = 64;        // tier slots per workgroup, slot 0 included
+constexpr int kMaxMiss = kBlock;     // misses collected per round
+constexpr int kLdsLimit = 160 * 1024;
+
+// Adaptive topology node.  Internal nodes are numbered 0..2^d-2 (root 0).
+// A child >= 0 is an internal node; a child < 0 is the leaf holding grey value
+// (-child - 1).  The left child covers [lo, split-1], the right [split, hi].
+struct TopoNode {
+  int32_t split, left, right, pad;
+};
+
+// Everything one launch of the median kernel needs.  Strides in elements.
+struct MedianArgs {
+  const void* src;
+  void* dst;
+  int64_t w, h, d;
+  int64_t srs, sss, drs, dss;
+  int64_t rank;       // K, 0-based
+  int32_t r;
+  int32_t bits;       // 8 or 16
+  int32_t stop;       // levels to descend (bits - drop_levels; adaptive: large)
+  int32_t seg_rows;   // output rows per workgroup
+  int32_t strips, segs;
+  int32_t ncols, cp;  // columns held per strip, padded byte pitch of a counter row
+  int32_t nslots;     // tier slots incl. slot 0 (tiered storage)
+  int32_t min_group;  // smallest lane group counted cooperatively
+  int32_t max_groups; // cooperative groups per level before falling back to direct sums
+  const TopoNode* topo;  // adaptive topology (device), else null
+};
+
+// Tile shape / strategy of one launch.
+struct TileConfig {
+  int32_t seg_rows;
+  int32_t nslots;     // 0 = as many as fit the LDS budget
+  int32_t min_group;
+  int32_t max_groups;
+  int32_t lds_budget; // bytes of LDS one workgroup may use
+  int32_t tiered_u8;  // 1 = tiered storage for u8 as well
+};
+
+// Launch the fused median kernel.  dims = 2 or 3.  Returns hipSuccess or the
+// launch error.
+hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive, bool tiered,
+                         hipStream_t stream);
+
+// LDS bytes a launch with these parameters needs.
+size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);
+
+// Adaptive topology pre-pass (Sec. III-C).  Builds `topo` (2^bits - 1 nodes)
+// from the input's global histogram mixed 1:1 with the histogram of its
+// clamp-to-edge box mean over the same window.  ws must hold
+// topology_workspace_bytes(bits, pixels) bytes.
+size_t topology_workspace_bytes(int bits, int64_t pixels);
+hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* ws, TopoNode* topo,
+                           hipStream_t stream);
+
+}  // namespace hrrm

@@ -1,0 +1,207 @@
+"""Bit-exact parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Sizes are chosen so the oracle finishes in seconds while the images still
+span several 256-column strips, several row segments and a ragged tail.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import announce, first_mismatch, to_dev, to_host
+from paper_1105_3829_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hrrm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1105_3829_amd as m
+    m.lib()
+    return m
+
+
+def _check2d(hrrm, img, r, variant="plain", **kw):
+    announce("2d", img.dtype, img.shape, "r=%d" % r, variant, kw)
+    got = to_host(hrrm.median2d(to_dev(img), r, variant=variant, **kw))
+    want = oracle.median2d(img, r)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def test_c0_full_image(hrrm):
+    img = datagen.uniform_u8(512, 512, seed=0)
+    _check2d(hrrm, img, 3)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 5, 15, 31, 32, 33, 63, 64])
+def test_u8_radii_ragged(hrrm, r):
+    img = datagen.uniform_u8(200, 300, seed=10 + r)
+    _check2d(hrrm, img, r)
+
+
+@pytest.mark.parametrize("r", [100, 127])
+def test_u8_large_radius(hrrm, r):
+    img = datagen.lowkey_u8(90, 270, seed=r)
+    _check2d(hrrm, img, r)
+    img = datagen.uniform_u8(60, 300, seed=r + 1)
+    _check2d(hrrm, img, r)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 5, 15, 31, 32, 50])
+def test_u16_xray_radii(hrrm, r):
+    img = datagen.xray_u16(180, 290, seed=20 + r)
+    _check2d(hrrm, img, r)
+
+
+@pytest.mark.parametrize("r", [1, 3, 7, 15])
+def test_u16_full_range_many_subtrees(hrrm, r):
+    # i.i.d. full-range values: medians scatter over many deep subtrees, which
+    # exercises slot eviction and the direct-count path
+    img = datagen.uniform_u16(150, 300, seed=30 + r)
+    _check2d(hrrm, img, r)
+
+
+@pytest.mark.parametrize("r", [1, 2, 4])
+def test_u16_extremes(hrrm, r):
+    g = np.random.default_rng(40 + r)
+    img = np.array([0, 1, 65534, 65535], dtype=np.uint16)[g.integers(0, 4, size=(70, 280))]
+    _check2d(hrrm, img, r)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (2, 1), (3, 3), (5, 1), (1, 7), (2, 257)])
+def test_tiny_images(hrrm, shape):
+    g = np.random.default_rng(sum(shape))
+    for dt, hi in ((np.uint8, 256), (np.uint16, 65536)):
+        img = g.integers(0, hi, size=shape).astype(dt)
+        for r in (0, 1, 3, 9):
+            _check2d(hrrm, img, r)
+
+
+def test_constant_and_two_level(hrrm):
+    _check2d(hrrm, np.full((40, 300), 77, np.uint8), 6)
+    _check2d(hrrm, np.full((40, 300), 4095, np.uint16), 6)
+    g = np.random.default_rng(3)
+    two = np.where(g.random((50, 270)) < 0.5, 0, 65535).astype(np.uint16)
+    _check2d(hrrm, two, 3)
+
+
+@pytest.mark.parametrize("variant", ["adaptive"])
+@pytest.mark.parametrize("kind,r", [("u8lowkey", 1), ("u8lowkey", 5), ("u8uniform", 3),
+                                    ("u16xray", 2), ("u16xray", 8), ("u16uniform", 3),
+                                    ("u8lowkey", 40)])
+def test_adaptive(hrrm, kind, r, variant):
+    if kind == "u8lowkey":
+        img = datagen.lowkey_u8(120, 300, seed=r)
+    elif kind == "u8uniform":
+        img = datagen.uniform_u8(100, 290, seed=r)
+    elif kind == "u16xray":
+        img = datagen.xray_u16(110, 280, seed=r)
+    else:
+        img = datagen.uniform_u16(90, 270, seed=r)
+    _check2d(hrrm, img, r, variant)
+
+
+@pytest.mark.parametrize("dt,r", [(np.uint16, 0), (np.uint16, 1), (np.uint16, 2), (np.uint16, 3),
+                                  (np.uint8, 5), (np.uint8, 7), (np.uint16, 7)])
+def test_3d(hrrm, dt, r):
+    if dt == np.uint16:
+        vol = datagen.xray_volume_u16(5, 40, 270, seed=50 + r)
+    else:
+        vol = np.stack([datagen.lowkey_u8(30, 100, seed=60 + z) for z in range(4)])
+    if r == 7:
+        vol = vol[:3, :24, :]
+    announce("3d", vol.dtype, vol.shape, "r=%d" % r)
+    got = to_host(hrrm.median3d(to_dev(vol), r))
+    want = oracle.median3d(vol, r)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+def test_3d_adaptive(hrrm):
+    vol = datagen.xray_volume_u16(4, 30, 260, seed=70)
+    announce("3d adaptive", vol.shape)
+    got = to_host(hrrm.median3d(to_dev(vol), 2, variant="adaptive"))
+    assert np.array_equal(got, oracle.median3d(vol, 2))
+
+
+def test_rank_and_reduced_precision(hrrm):
+    img = datagen.xray_u16(90, 280, seed=80)
+    r = 4
+    n = (2 * r + 1) ** 2
+    for k in (0, 1, n // 4, n - 1):
+        announce("rank", k)
+        got = to_host(hrrm.rank2d(to_dev(img), r, k))
+        assert np.array_equal(got, oracle.rank2d(img, r, k)), k
+    for drop in (1, 4, 8, 16):
+        announce("drop", drop)
+        got = to_host(hrrm.rank2d(to_dev(img), r, (n - 1) // 2, drop_levels=drop))
+        assert np.array_equal(got, oracle.rank2d(img, r, None, drop_bits=drop)), drop
+    img8 = datagen.uniform_u8(80, 270, seed=81)
+    for drop in (0, 3, 8):
+        got = to_host(hrrm.rank2d(to_dev(img8), r, (n - 1) // 2, drop_levels=drop))
+        assert np.array_equal(got, oracle.rank2d(img8, r, None, drop_bits=drop)), drop
+
+
+def test_strided_rows(hrrm):
+    import torch
+    img = datagen.uniform_u8(70, 300, seed=90)
+    big = torch.zeros((70, 333), dtype=torch.uint8, device="cuda:0")
+    big[:, :300] = to_dev(img)
+    view = big[:, :300]
+    out_big = torch.full((70, 320), 7, dtype=torch.uint8, device="cuda:0")
+    out = out_big[:, :300]
+    hrrm.median2d(view, 5, out=out)
+    got = to_host(out_big)
+    assert np.array_equal(got[:, :300], oracle.median2d(img, 5))
+    assert (got[:, 300:] == 7).all()  # nothing written past the width
+
+
+def test_repeatable(hrrm):
+    img = datagen.xray_u16(200, 520, seed=91)
+    d = to_dev(img)
+    a = to_host(hrrm.median2d(d, 9))
+    for _ in range(3):
+        assert np.array_equal(to_host(hrrm.median2d(d, 9)), a)
+
+
+def test_c1_full_size_sampled(hrrm):
+    # the headline workload at full size: u16 4096^2, r = 15, both variants;
+    # the oracle checks 20000 sampled pixels plus full borders of rows/columns
+    img = datagen.xray_u16(4096, 4096, seed=1)
+    d = to_dev(img)
+    g = np.random.default_rng(1)
+    ys = np.concatenate([g.integers(0, 4096, 20000), np.zeros(512, int), np.full(512, 4095)])
+    xs = np.concatenate([g.integers(0, 4096, 20000), g.integers(0, 4096, 1024)])
+    want = oracle.rank2d_at(img, 15, xs, ys)
+    for variant in ("plain", "adaptive"):
+        announce("c1 full", variant)
+        got = to_host(hrrm.median2d(d, 15, variant=variant))
+        assert np.array_equal(got[ys, xs], want), variant
+
+
+def test_validation_errors(hrrm):
+    import torch
+    L = hrrm.lib()
+    ctx = hrrm.context(0).handle
+    d = torch.zeros((10, 10), dtype=torch.uint8, device="cuda:0")
+    o = torch.zeros((10, 10), dtype=torch.uint8, device="cuda:0")
+    s, t = d.data_ptr(), o.data_ptr()
+    assert L.hrrm_median2d(ctx, s, t, 1, 10, 10, 10, 10, -1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median2d(ctx, s, t, 1, 10, 10, 10, 10, 128, 0, None) == hrrm.EUNSUPPORTED
+    assert L.hrrm_median2d(ctx, s, t, 3, 10, 10, 10, 10, 1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median2d(ctx, s, t, 1, 10, 10, 9, 10, 1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median2d(ctx, None, t, 1, 10, 10, 10, 10, 1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median2d(ctx, s, s + 5, 1, 10, 10, 10, 10, 1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median2d(ctx, s, t, 1, 10, 10, 10, 10, 1, 7, None) == hrrm.EINVAL
+    assert L.hrrm_median2d(ctx, s, t, 1, 0, 10, 10, 10, 1, 0, None) == hrrm.OK
+    assert L.hrrm_median2d(None, s, t, 1, 10, 10, 10, 10, 1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median3d(ctx, s, t, 1, 10, 5, 2, 10, 40, 10, 50, 1, 0, None) == hrrm.EINVAL
+    assert L.hrrm_median3d(ctx, s, t, 1, 5, 2, 2, 5, 10, 5, 10, 8, 0, None) == hrrm.EUNSUPPORTED
+    assert L.hrrm_rank2d(ctx, s, t, 1, 10, 10, 10, 10, 1, 9, 0, 0, None) == hrrm.EINVAL
+    assert L.hrrm_rank2d(ctx, s, t, 1, 10, 10, 10, 10, 1, 4, 9, 0, None) == hrrm.EINVAL
+    assert L.hrrm_rank2d(ctx, s, t, 1, 10, 10, 10, 10, 1, 4, 2, 1, None) == hrrm.EINVAL
+    odd = torch.zeros(21, dtype=torch.uint8, device="cuda:0").data_ptr() + 1
+    assert L.hrrm_median2d(ctx, odd, t, 2, 5, 2, 5, 5, 1, 0, None) == hrrm.EINVAL
+    torch.cuda.synchronize()
+    assert (o == 0).all()  # rejected calls enqueue nothing
