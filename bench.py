@@ -1,0 +1,194 @@
+#!/usr/bin/env python
+"""Benchmark of the running-median hot path on one MI355X.
+
+Default workload: 16-bit 4096 x 4096 X-ray-like image (12-bit Gaussian mixture
+plus a smooth ramp), radius 15 (31 x 31 window), clamp-to-edge, plain
+(uniform-tree) variant.  One step = one full filter pass over one image that is
+already resident in HBM; the timed region rotates over input/output copies
+larger than the 256 MB last-level cache so every step reads from HBM.
+
+Prints ONE JSON line.  Besides the throughput it carries
+  * roofline: the LDS bound of the kernel (algorithmic LDS work per pixel from
+    the input histogram) against the LDS peak, the kernel time
+    taken from HIP events on the launch stream, with the HBM view alongside;
+  * cpu_baseline: the brute-force CPU oracle timed on a band of full rows of
+    the same image on this host's cores.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload c1] [--r 15]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "output Mpix/s (u16 4096², r=15) + % HBM/LDS roofline; serving p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+# LDS: 256 CUs x 32 banks x 4 B per clock x 2.4 GHz (derivation in the design doc)
+LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
+
+
+def workload(name: str, r: int):
+    from paper_1105_3829_amd import datagen
+    if name == "c1":
+        return datagen.xray_u16(4096, 4096, seed=1), "u16 4096x4096 X-ray-like mixture + ramp"
+    if name == "c0":
+        return datagen.uniform_u8(512, 512, seed=0), "u8 512x512 uniform"
+    if name == "c2":
+        return datagen.lowkey_u8(8192, 8192, seed=2), "u8 8192x8192 low-key"
+    raise SystemExit("unknown workload %s" % name)
+
+
+def lds_work_per_pixel(img) -> tuple:
+    """Algorithmic LDS dword-operations per output pixel of the uniform
+    on-demand method: 2*zbar counter updates (one removal, one insertion per
+    column per row; an update touches the levels where the value's bit is 0)
+    plus 2*d column-counter reads (one entering, one leaving column per level
+    of the descent).  zbar is exact for this input (from its histogram)."""
+    import numpy as np
+    d = 8 * img.dtype.itemsize
+    hist = np.bincount(img.ravel(), minlength=1 << d).astype(np.float64)
+    ones = np.array([bin(v).count("1") for v in range(1 << d)], dtype=np.float64)
+    zbar = d - float((hist * ones).sum() / hist.sum())
+    return 2.0 * zbar + 2.0 * d, zbar, d
+
+
+def cpu_baseline(img, r: int, seconds_target: float = 10.0):
+    import numpy as np
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    h, w = img.shape
+    # calibrate on a thin band, then time a band sized for ~seconds_target
+    probe = np.ascontiguousarray(img[: min(h, 16 + 2 * r)])
+    t = time.perf_counter()
+    oracle.median2d(probe, r, threads=threads)
+    rate = probe.size / max(time.perf_counter() - t, 1e-6)
+    rows = int(max(32, min(h, seconds_target * rate / w)))
+    band = np.ascontiguousarray(img[:rows])
+    t = time.perf_counter()
+    oracle.median2d(band, r, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": round(band.size / dt / 1e6, 4), "unit": "Mpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "rows 0..%d of the same image (%d x %d pixels, clamp at the image's own "
+                      "top border), brute-force nth_element per window, %.1f s" % (rows - 1, w, rows,
+                                                                                  dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--r", type=int, default=15)
+    ap.add_argument("--variant", default="plain")
+    ap.add_argument("--copies", type=int, default=0, help="input/output copies rotated over")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of one image (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the filter would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1105_3829_amd as hrrm
+
+    img, desc = workload(args.workload, args.r)
+    h, w = img.shape
+    dev = torch.device("cuda:0")
+    host = torch.from_numpy(img)
+    if host.dtype == torch.uint16:
+        base = host.view(torch.int16).to(dev).view(torch.uint16)
+    else:
+        base = host.to(dev)
+    nbytes = img.nbytes
+    copies = args.copies or max(2, int(np.ceil(2 * 256 * 2**20 / (2 * nbytes))) + 1)
+    srcs = [base.clone() for _ in range(copies)]
+    outs = [torch.empty_like(base) for _ in range(copies)]
+    ctx = hrrm.context(0)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(i):
+        ctx.median2d(srcs[i % copies], args.r, variant=args.variant, out=outs[i % copies],
+                     stream=stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if args.copy_calibration:
+        tmp = torch.empty_like(base)
+        tmp.copy_(srcs[0])
+        torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        step(i)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    pixels = h * w
+    value = pixels / (ms_per_step * 1e-3) / 1e6
+
+    a_ops, zbar, d = lds_work_per_pixel(img)
+    lds_bytes_launch = a_ops * 4.0 * pixels
+    hbm_bytes_launch = 2.0 * img.dtype.itemsize * pixels
+    lds_gbs = lds_bytes_launch / (kernel_ms * 1e-3) / 1e9
+    hbm_gbs = hbm_bytes_launch / (kernel_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "hbm_traffic_%s_r%d_%s.json" % (args.workload, args.r,
+                                                                           args.variant))
+    if os.path.exists(tfile):
+        try:
+            traffic = json.load(open(tfile)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u%d" % (8 * img.dtype.itemsize),
+        "data": "synthetic",
+        "config": {"workload": "%s, r=%d (%dx%d window), clamp-to-edge, %s tree" % (
+            desc, args.r, 2 * args.r + 1, 2 * args.r + 1, args.variant), "width": w, "height": h,
+            "r": args.r, "variant": args.variant, "input_copies": copies},
+        "roofline": {"bound": "lds", "achieved": round(lds_gbs, 2), "peak": LDS_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(lds_gbs / LDS_PEAK_GBS, 5),
+                     "traffic": traffic, "kernel_ms": round(kernel_ms, 4),
+                     "lds_dword_ops_per_pixel": round(a_ops, 3), "zbar": round(zbar, 4),
+                     "hbm": {"achieved": round(hbm_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(hbm_gbs / HBM_PEAK_GBS, 6),
+                             "bytes_per_launch": hbm_bytes_launch}},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(img, args.r)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
