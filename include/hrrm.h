@@ -149,6 +149,33 @@ int32_t hrrm_batch_capacity(void);
 
 /* ---- Tile configuration / autotuning ------------------------------------- */
 
+/* Launch shape and strategy of the fused kernel for one (dtype, dims, r,
+ * variant).  Every configuration gives bit-identical output; they differ in
+ * speed only.
+ *   seg_rows   : output rows one workgroup produces (its column trees are built
+ *                once per segment: 2r+1 rows, then updated row by row)
+ *   nslots     : tier slots per workgroup for trees deeper than one tier
+ *                (0 = as many as lds_budget allows)
+ *   min_group  : smallest group of lanes sharing a tree node whose window count
+ *                is formed cooperatively (prefix sum over the wave); smaller
+ *                groups sum their 2r+1 column counters directly
+ *   max_groups : cooperative groups per level before the rest count directly
+ *   lds_budget : LDS bytes one workgroup may use (caps nslots; sets occupancy)
+ *   tiered_u8  : 1 = 8-bit data also uses tiered storage (else dense) */
+typedef struct {
+  int32_t seg_rows, nslots, min_group, max_groups, lds_budget, tiered_u8;
+} hrrm_tile_config;
+
+/* Set (cfg != NULL) or clear (cfg == NULL) the context's tile configuration
+ * for one key.  EINVAL for out-of-range fields. */
+int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
+                         hrrm_variant variant, const hrrm_tile_config* cfg);
+
+/* The configuration a call of this shape would use now. */
+int hrrm_get_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
+                         hrrm_variant variant, int64_t width, int64_t height, int64_t depth,
+                         hrrm_tile_config* out);
+
 /* Time the tile candidates for (dtype, r, variant) on a synthetic image of
  * width x height drawn on the device, keep the fastest in the context's tile
  * table, and return its index in *best (may be NULL).  Synchronises the

@@ -44,6 +44,15 @@ class _Image(ctypes.Structure):
                 ("r", ctypes.c_int32)]
 
 
+class TileConfig(ctypes.Structure):
+    _fields_ = [("seg_rows", ctypes.c_int32), ("nslots", ctypes.c_int32),
+                ("min_group", ctypes.c_int32), ("max_groups", ctypes.c_int32),
+                ("lds_budget", ctypes.c_int32), ("tiered_u8", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class _Request(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("width", ctypes.c_int64), ("height", ctypes.c_int64),
                 ("src_row_stride", ctypes.c_int64), ("dtype", ctypes.c_int32),
@@ -79,6 +88,9 @@ def lib():
                 "hrrm_batch_capacity": ([], i32),
                 "hrrm_autotune": ([vp, i32, i32, i32, i64, i64, cp, ctypes.POINTER(i32)], i32),
                 "hrrm_load_tuning": ([vp, cp], i32),
+                "hrrm_set_tile_config": ([vp, i32, i32, i32, i32, ctypes.POINTER(TileConfig)], i32),
+                "hrrm_get_tile_config": ([vp, i32, i32, i32, i32, i64, i64, i64,
+                                          ctypes.POINTER(TileConfig)], i32),
                 "hrrm_server_create": ([vp, ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)], i32),
                 "hrrm_server_submit": ([vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)],
                                        i32),
@@ -218,6 +230,23 @@ class Context:
                                   cache_path.encode() if cache_path else None, ctypes.byref(best)))
         return best.value
 
+    def set_tile(self, dtype: int, dims: int, r: int, variant="plain", cfg=None, **fields):
+        """Set the tile configuration for one key (cfg=None and no fields: reset)."""
+        if cfg is None and fields:
+            cfg = self.get_tile(dtype, dims, r, variant)
+        if cfg is not None:
+            for k, v in fields.items():
+                setattr(cfg, k, int(v))
+        check(lib().hrrm_set_tile_config(self._h, dtype, dims, r, _variant_code(variant),
+                                         ctypes.byref(cfg) if cfg is not None else None))
+
+    def get_tile(self, dtype: int, dims: int, r: int, variant="plain", width: int = 4096,
+                 height: int = 4096, depth: int = 1) -> TileConfig:
+        cfg = TileConfig()
+        check(lib().hrrm_get_tile_config(self._h, dtype, dims, r, _variant_code(variant), width,
+                                         height, depth, ctypes.byref(cfg)))
+        return cfg
+
     def load_tuning(self, path: str):
         check(lib().hrrm_load_tuning(self._h, path.encode()))
 
@@ -260,7 +289,8 @@ def median2d_batched(srcs, radii, outs=None, stream=None):
 EXPORTED_SYMBOLS: List[str] = [
     "hrrm_last_error", "hrrm_version", "hrrm_ctx_create", "hrrm_ctx_destroy", "hrrm_ctx_reserve",
     "hrrm_median2d", "hrrm_median3d", "hrrm_rank2d", "hrrm_median2d_batched",
-    "hrrm_batch_capacity", "hrrm_autotune", "hrrm_load_tuning", "hrrm_server_create",
+    "hrrm_batch_capacity", "hrrm_autotune", "hrrm_load_tuning", "hrrm_set_tile_config",
+    "hrrm_get_tile_config", "hrrm_server_create",
     "hrrm_server_submit", "hrrm_server_poll", "hrrm_server_release", "hrrm_server_cancel",
     "hrrm_server_now", "hrrm_server_destroy",
 ]

@@ -24,6 +24,7 @@ ARCH = os.environ.get("HRRM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = [
     "median_kernels.hip",
+    "median_tiered.hip",
     "topology.hip",
     "batched.hip",
     "hrrm_api.cpp",

@@ -44,8 +44,14 @@ const char* last_error() { return g_err.c_str(); }
 TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
                         int64_t d) {
   TileConfig t{};
+  const bool tiered = bytes == 2;
+  const int span = 2 * r + 1;
   t.min_group = 2;
-  t.max_groups = 64;
+  // tiered storage: the wave's window counts of one tier come from cooperative
+  // prefix sums (one per subtree the wave touches, about 170 instructions each)
+  // or from per-lane sums over the 2r+1 columns (about 6.5 per column); take the
+  // prefix sums while they are cheaper
+  t.max_groups = tiered ? std::max(1, (int)((6.5 * span + 40) / 170)) : 64;
   t.nslots = 0;
   t.tiered_u8 = 0;
   t.lds_budget = 80 * 1024;
@@ -55,11 +61,10 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   const int64_t strips = (w + kBlock - 1) / kBlock;
   const int64_t want_wg = 2048;
   int64_t rows = (strips * h * d) / want_wg;
-  const int64_t min_rows = std::max<int64_t>(16, 2 * (2 * r + 1));
+  const int64_t min_rows = std::max<int64_t>(16, 2 * r + 1);
   rows = std::max<int64_t>(rows, min_rows);
   rows = std::min<int64_t>(rows, 512);
   t.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(rows, h));
-  (void)bytes;
   (void)dims;
   (void)adaptive;
   return t;
@@ -157,7 +162,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
 
   if (tiered) {
     const size_t meta = median_lds_bytes(bytes, adaptive, true, a.ncols, a.cp, 0);
-    const size_t slot_bytes = (size_t)kTierNodes * a.cp;
+    const size_t slot_bytes = (size_t)a.cp * 16;  // one 16-byte tier vector per column
     const size_t budget = (size_t)std::min(std::max(t.lds_budget, 16 * 1024), kLdsLimit);
     int fit = budget > meta ? (int)((budget - meta) / slot_bytes) : 0;
     int ns = t.nslots > 0 ? t.nslots : fit;
@@ -312,6 +317,51 @@ int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype
   return run_filter(c, d_src, d_dst, dtype, width, height, depth, src_row_stride,
                     src_slice_stride, dst_row_stride, dst_slice_stride, r, (s * s * s - 1) / 2, 0,
                     variant, 3, (hipStream_t)hip_stream, nullptr);
+}
+
+static bool tile_ok(const hrrm_tile_config* c) {
+  return c->seg_rows >= 1 && c->nslots >= 0 && c->nslots <= kMaxSlots && c->min_group >= 1 &&
+         c->min_group <= 65 && c->max_groups >= 0 && c->lds_budget >= 16 * 1024 &&
+         c->lds_budget <= kLdsLimit && (c->tiered_u8 == 0 || c->tiered_u8 == 1);
+}
+
+int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
+                         hrrm_variant variant, const hrrm_tile_config* cfg) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  if ((dtype != HRRM_U8 && dtype != HRRM_U16) || (dims != 2 && dims != 3) || r < 0 ||
+      (variant != HRRM_PLAIN && variant != HRRM_ADAPTIVE))
+    return fail(HRRM_EINVAL, "bad tile key");
+  if (cfg && !tile_ok(cfg)) return fail(HRRM_EINVAL, "tile configuration out of range");
+  const int bytes = dtype == HRRM_U8 ? 1 : 2;
+  const int ad = variant == HRRM_ADAPTIVE;
+  auto& v = c->tuned;
+  v.erase(std::remove_if(v.begin(), v.end(), [&](const TunedEntry& e) {
+            return e.bytes == bytes && e.dims == dims && e.r == r && e.adaptive == ad;
+          }), v.end());
+  if (cfg) {
+    TunedEntry e{bytes, dims, r, ad, TileConfig{cfg->seg_rows, cfg->nslots, cfg->min_group,
+                                                cfg->max_groups, cfg->lds_budget, cfg->tiered_u8},
+                 0.0};
+    v.push_back(e);
+  }
+  return HRRM_OK;
+}
+
+int hrrm_get_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
+                         hrrm_variant variant, int64_t width, int64_t height, int64_t depth,
+                         hrrm_tile_config* out) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c || !out) return fail(HRRM_EINVAL, "null argument");
+  if ((dtype != HRRM_U8 && dtype != HRRM_U16) || (dims != 2 && dims != 3) || r < 0)
+    return fail(HRRM_EINVAL, "bad tile key");
+  const TileConfig t = c->tile_for(dtype == HRRM_U8 ? 1 : 2, dims, r, variant == HRRM_ADAPTIVE,
+                                   width, height, dims == 3 ? depth : 1);
+  *out = hrrm_tile_config{t.seg_rows, t.nslots, t.min_group, t.max_groups, t.lds_budget,
+                          t.tiered_u8};
+  return HRRM_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,669 @@
+// Tiered running-median kernel for gfx950: 16-bit data (uniform or adaptive
+// tree) and adaptive 8-bit data.
+//
+// Method: Alekseychuk, "Hierarchical Recursive Running Median".  Every column
+// of a strip keeps an implicit interval-occurrences tree over the 2r+1 rows of
+// the current window (Sec. III, Sec. III-A): one counter per left node, the
+// top node elided.  A row step removes one value from and inserts one value
+// into each column tree (Sec. III-B).  The descent of get_order_statistic
+// (Sec. III) compares window counts of left nodes with K minus the
+// left-occurrence accumulator, level by level.
+//
+// Tiers.  The tree is cut into 4-level subtrees ("tiers").  A column keeps the
+// 15 left-node counters of one tier subtree as a 16-byte vector, so one 128-bit
+// LDS read delivers a column's counts for four levels and the descent resolves
+// four levels per window count (radix 16).  Tier 1 (the top) is always held.
+// Deeper subtrees are materialised in LDS slots only when a pixel of the current
+// row descends into them and are then maintained by the row updates while rows
+// keep using them (least recently used replacement) - the paper's on-demand
+// principle (window counts only for nodes the descent visits) applied to the
+// column trees.
+//
+// Window counts of a tier for the 64 pixels of a wave:
+//  * cooperative: lanes sharing a slot read the counters of the column entering
+//    and leaving their window; a DPP prefix sum over the wave gives every
+//    pixel's count as the count of the wave's first window plus the running
+//    sum of (entering - leaving) - the paper's elementary window update
+//    (one add, one subtract per node), for 64 pixels at once;
+//  * direct: each lane sums the 2r+1 column vectors of its own window (the
+//    paper's non-elementary catch-up), used when the wave's pixels are spread
+//    over several subtrees.
+// When every slot already serves the current row, the wave builds the missing
+// subtree's column vectors for just its own 64+2r columns from the raw window
+// values in a per-wave scratch area and sums those instead.
+//
+// Uniform trees locate tier roots arithmetically (prefix of the value) and map
+// them to slots with a direct table; adaptive trees (Sec. III-C) follow the
+// topology table and map tier roots with a small hash.
+#include "hrrm_internal.h"
+#include "wave.hpp"
+
+namespace hrrm {
+namespace {
+
+constexpr int kMissCap = 64;
+constexpr int kSmap = 16 + 256 + 4096;  // roots of tiers 2..4 of a 16-bit uniform tree
+constexpr uint32_t kNone = 0xffu;
+
+struct TierState {
+  uint4 lut[16];                 // uniform insertion masks of a 4-level subtree
+  uint8_t smap[kSmap];           // uniform: tier-root key -> slot (kNone = absent)
+  uint32_t ht[kHash];            // adaptive: (node + 1) << 8 | slot, 0 = empty
+  int32_t key[kMaxSlots], lo[kMaxSlots], hi[kMaxSlots], dep[kMaxSlots], stamp[kMaxSlots];
+  int32_t miss_n[3];
+  int32_t flag[3][kWaves];
+  int32_t reb_n;
+  int32_t pad;
+  int32_t miss[kMissCap][4];     // key, lo, hi, depth of a subtree root nobody holds
+  int32_t reb[kMaxSlots][4];     // slot, key, lo, depth of a slot to rebuild
+};
+
+__device__ __forceinline__ uint32_t ht_hash(int key) {
+  return ((uint32_t)key * 2654435761u) >> 25;  // 7 bits for kHash = 128
+}
+
+__device__ __forceinline__ int ht_find(const uint32_t* ht, int key) {
+  const uint32_t h = ht_hash(key), tag = (uint32_t)(key + 1);
+  for (int i = 0; i < kHash; ++i) {
+    const uint32_t e = ht[(h + i) & (kHash - 1)];
+    if (e == 0) return -1;
+    if ((e >> 8) == tag) return (int)(e & 0xffu);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void ht_insert(uint32_t* ht, int key, int slot) {
+  const uint32_t h = ht_hash(key);
+  for (int i = 0; i < kHash; ++i) {
+    uint32_t& e = ht[(h + i) & (kHash - 1)];
+    if (e == 0) {
+      e = ((uint32_t)(key + 1) << 8) | (uint32_t)slot;
+      return;
+    }
+  }
+}
+
+// Uniform tree: table index of the tier subtree rooted at depth `dep` (4, 8,
+// 12) containing values with prefix `pre` = value >> (bits - dep).
+__device__ __forceinline__ int ukey(int dep, int pre) { return (((1 << dep) - 16) / 15) + pre; }
+
+// Bytes of the levels of a tier subtree that are maintained: levels
+// 0..nlev-1 occupy bytes 0 .. 2^nlev - 2.
+__device__ __forceinline__ uint4 level_mask(int nlev) {
+  const int nb = (1 << nlev) - 1;  // bytes kept
+  uint4 m;
+  m.x = nb >= 4 ? 0xffffffffu : (nb <= 0 ? 0u : (0xffffffffu >> (32 - 8 * nb)));
+  m.y = nb >= 8 ? 0xffffffffu : (nb <= 4 ? 0u : (0xffffffffu >> (32 - 8 * (nb - 4))));
+  m.z = nb >= 12 ? 0xffffffffu : (nb <= 8 ? 0u : (0xffffffffu >> (32 - 8 * (nb - 8))));
+  m.w = nb >= 16 ? 0xffffffffu : (nb <= 12 ? 0u : (0xffffffffu >> (32 - 8 * (nb - 12))));
+  return m;
+}
+
+__device__ __forceinline__ uint4 and4(uint4 a, uint4 b) {
+  return make_uint4(a.x & b.x, a.y & b.y, a.z & b.z, a.w & b.w);
+}
+__device__ __forceinline__ uint4 add4(uint4 a, uint4 b) {
+  return make_uint4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ uint4 sub4(uint4 a, uint4 b) {
+  return make_uint4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+
+__device__ __forceinline__ uint4& vec(uint8_t* slots, size_t cp16, int slot, int col) {
+  return *(uint4*)(slots + (size_t)slot * cp16 + (size_t)col * 16);
+}
+
+// Insertion mask of value v in the adaptive subtree rooted at internal node
+// `node` (depth dep, interval starting at lo): walk at most four levels of the
+// topology, marking the left nodes the value counts in.
+__device__ __forceinline__ uint4 amask(const TopoNode* topo, int node, int dep, int stop, int v) {
+  uint32_t m[4] = {0u, 0u, 0u, 0u};
+  int p = 1;
+#pragma unroll
+  for (int k = 0; k < kTierLevels; ++k) {
+    if (node < 0 || dep + k >= stop) break;
+    const TopoNode t = topo[node];
+    const bool left = v < t.split;
+    if (left) {
+      const int b = p - 1;
+      m[b >> 2] |= 1u << ((b & 3) * 8);
+    }
+    node = left ? t.left : t.right;
+    p = 2 * p + (left ? 0 : 1);
+  }
+  return make_uint4(m[0], m[1], m[2], m[3]);
+}
+
+// Count of node q (0..14) from the packed window counts: word 2i holds nodes
+// 4i and 4i+2, word 2i+1 nodes 4i+1 and 4i+3 (16-bit fields).
+__device__ __forceinline__ uint32_t wsel(const uint32_t (&W)[8], int q) {
+  const int i = q >> 2;
+  const bool odd = q & 1;
+  const uint32_t a0 = odd ? W[1] : W[0];
+  const uint32_t a1 = odd ? W[3] : W[2];
+  const uint32_t a2 = odd ? W[5] : W[4];
+  const uint32_t a3 = odd ? W[7] : W[6];
+  const uint32_t b0 = (i & 1) ? a1 : a0;
+  const uint32_t b1 = (i & 1) ? a3 : a2;
+  const uint32_t c = (i & 2) ? b1 : b0;
+  return (q & 2) ? (c >> 16) : (c & 0xffffu);
+}
+
+// Cooperative window counts of slot s for all lanes (see file comment); lanes
+// with member=true keep the result.  All 64 lanes must be active.
+__device__ __forceinline__ void coop_counts(uint32_t (&W)[8], const uint8_t* slots, size_t cp16,
+                                            int s, bool member, int lx, int span, int lane,
+                                            int wbase) {
+  const uint8_t* sb = slots + (size_t)s * cp16;
+  const uint4 vin = *(const uint4*)(sb + (size_t)(lx + span) * 16);  // column x + r
+  const uint4 vout = *(const uint4*)(sb + (size_t)lx * 16);          // column x - r - 1
+  uint32_t ex[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  if (span > 64) {  // the first window spans more than the wave's 64 leaving columns
+    for (int k = 64 + lane; k < span; k += 64) {
+      const uint4 e = *(const uint4*)(sb + (size_t)(wbase + k) * 16);
+      const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ex[2 * i] += ev[i] & 0x00ff00ffu;
+        ex[2 * i + 1] += (ev[i] >> 8) & 0x00ff00ffu;
+      }
+    }
+  }
+  const int bl = span <= 64 ? span - 1 : 63;
+  const uint32_t vi[4] = {vin.x, vin.y, vin.z, vin.w};
+  const uint32_t vo[4] = {vout.x, vout.y, vout.z, vout.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t il = wave_scan(vi[i] & 0x00ff00ffu);
+    const uint32_t ih = wave_scan((vi[i] >> 8) & 0x00ff00ffu);
+    const uint32_t ol = wave_scan(vo[i] & 0x00ff00ffu);
+    const uint32_t oh = wave_scan((vo[i] >> 8) & 0x00ff00ffu);
+    uint32_t bl0 = readlane_u(ol, bl), bh0 = readlane_u(oh, bl);
+    if (span > 64) {
+      bl0 += readlane_u(wave_scan(ex[2 * i]), 63);
+      bh0 += readlane_u(wave_scan(ex[2 * i + 1]), 63);
+    }
+    if (member) {
+      W[2 * i] = bl0 + il - ol;
+      W[2 * i + 1] = bh0 + ih - oh;
+    }
+  }
+}
+
+// Direct window counts: this lane sums the 2r+1 column vectors of its window.
+// Bytes are summed `batch` columns at a time (no byte overflows) and then
+// widened to 16-bit fields.
+__device__ __forceinline__ void direct_counts(uint32_t (&W)[8], const uint8_t* slots, size_t cp16,
+                                              int s, int lx, int span, int batch) {
+  const uint8_t* p = slots + (size_t)s * cp16 + (size_t)(lx + 1) * 16;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) W[i] = 0;
+  for (int j0 = 0; j0 < span; j0 += batch) {
+    const int jn = j0 + batch < span ? j0 + batch : span;
+    uint32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll 4
+    for (int j = j0; j < jn; ++j) {
+      const uint4 v = *(const uint4*)(p + (size_t)j * 16);
+      a0 += v.x;
+      a1 += v.y;
+      a2 += v.z;
+      a3 += v.w;
+    }
+    W[0] += a0 & 0x00ff00ffu;
+    W[1] += (a0 >> 8) & 0x00ff00ffu;
+    W[2] += a1 & 0x00ff00ffu;
+    W[3] += (a1 >> 8) & 0x00ff00ffu;
+    W[4] += a2 & 0x00ff00ffu;
+    W[5] += (a2 >> 8) & 0x00ff00ffu;
+    W[6] += a3 & 0x00ff00ffu;
+    W[7] += (a3 >> 8) & 0x00ff00ffu;
+  }
+}
+
+// Wave-local stand-in for a subtree no slot holds: the wave's lanes build its
+// column vectors for the 64+2r columns the wave's windows cover, from the raw
+// window values (loads coalesced across lanes), into the wave's scratch area.
+// The caller then sums them per lane like a held slot.  Nothing is kept for
+// later rows.
+template <typename T, bool ADAPT, bool D3>
+__device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict__ src,
+                                              const MedianArgs& a, const TierState* ts,
+                                              const TopoNode* topo, int64_t x0w, int64_t y,
+                                              int64_t z, int lane, int span, int node, int rlo,
+                                              int rhi, int rdep) {
+  const int r = a.r, zr = D3 ? r : 0, bits = a.bits, stop = a.stop;
+  const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+  for (int c = lane; c <= 64 + span - 1; c += 64) {
+    const int64_t cx = clampi(x0w - r - 1 + c, a.w - 1);
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    for (int dz = -zr; dz <= zr; ++dz) {
+      const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+#pragma unroll 4
+      for (int j = -r; j <= r; ++j) {
+        const int v = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
+        if (v >= rlo && v <= rhi) {
+          if constexpr (ADAPT)
+            acc = add4(acc, amask(topo, node, rdep, stop, v));
+          else
+            acc = add4(acc, and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim));
+        }
+      }
+    }
+    *(uint4*)(scr + (size_t)c * 16) = acc;
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Slot assignment for this round's misses (thread 0): least recently used
+// slots not used by the current row are replaced.  Adaptive trees also drop the
+// held subtrees below a replaced slot (their updates walk down from the top and
+// stop at the first subtree no slot holds).
+template <bool ADAPT>
+__device__ void assign_slots(TierState* ts, int nmiss, int stamp, int nslots) {
+  int nreb = 0;
+  for (int i = 0; i < nmiss; ++i) {
+    const int key = ts->miss[i][0];
+    const bool held = ADAPT ? ht_find(ts->ht, key) >= 0 : ts->smap[key] != kNone;
+    if (held) continue;  // duplicate from another wave
+    int victim = -1, best = 0x7fffffff;
+    for (int s = 1; s < nslots; ++s) {
+      const int st = ts->stamp[s];
+      if (st != stamp && st < best) {
+        best = st;
+        victim = s;
+      }
+    }
+    if (victim < 0) continue;  // every slot serves this row: these pixels count directly
+    if (ts->key[victim] >= 0) {
+      if constexpr (ADAPT) {
+        const int vlo = ts->lo[victim], vhi = ts->hi[victim], vdep = ts->dep[victim];
+        for (int s = 1; s < nslots; ++s)
+          if (ts->key[s] >= 0 &&
+              (s == victim || (ts->dep[s] > vdep && ts->lo[s] >= vlo && ts->lo[s] <= vhi))) {
+            ts->key[s] = -1;
+            ts->stamp[s] = -1;
+          }
+        for (int h = 0; h < kHash; ++h) ts->ht[h] = 0;
+        for (int s = 1; s < nslots; ++s)
+          if (ts->key[s] >= 0) ht_insert(ts->ht, ts->key[s], s);
+      } else {
+        ts->smap[ts->key[victim]] = (uint8_t)kNone;
+      }
+    }
+    ts->key[victim] = key;
+    ts->lo[victim] = ts->miss[i][1];
+    ts->hi[victim] = ts->miss[i][2];
+    ts->dep[victim] = ts->miss[i][3];
+    ts->stamp[victim] = stamp;
+    if constexpr (ADAPT)
+      ht_insert(ts->ht, key, victim);
+    else
+      ts->smap[key] = (uint8_t)victim;
+    ts->reb[nreb][0] = victim;
+    ts->reb[nreb][1] = key;
+    ts->reb[nreb][2] = ts->miss[i][1];
+    ts->reb[nreb][3] = ts->miss[i][3];
+    ++nreb;
+  }
+  ts->reb_n = nreb;
+}
+
+template <typename T, bool ADAPT, bool D3>
+__global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const T* __restrict__ src = (const T*)a.src;
+  T* __restrict__ dst = (T*)a.dst;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = a.r, ncols = a.ncols, bits = a.bits, stop = a.stop;
+  const int span = 2 * r + 1;
+  const int zr = D3 ? r : 0;
+  const size_t cp16 = (size_t)a.cp * 16;  // bytes of one slot (cp >= ncols columns)
+  const TopoNode* __restrict__ topo = a.topo;
+
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int strip = bid % a.strips;
+  const int rest = bid / a.strips;
+  const int seg = rest % a.segs;
+  const int64_t z = rest / a.segs;
+  const int64_t x0 = (int64_t)strip * kBlock;
+  const int64_t yb = (int64_t)seg * a.seg_rows;
+  const int64_t ye = yb + a.seg_rows < a.h ? yb + a.seg_rows : a.h;
+
+  uint8_t* slots = lds;
+  TierState* ts = (TierState*)(lds + align16((size_t)a.nslots * cp16));
+  // per-wave scratch of (64 + 2r + 1) column vectors for subtrees no slot holds
+  uint8_t* scr = lds + align16((size_t)a.nslots * cp16) + align16(sizeof(TierState)) +
+                 (size_t)wv * (64 + span) * 16;
+  const int root = ADAPT ? topo[(1 << bits) - 1].split : 1;
+  const int maxv = (1 << bits) - 1;
+  const int ntiers = (bits + kTierLevels - 1) / kTierLevels;
+
+  // ---- set-up: tables, empty slots
+  if (tid < 16) {
+    uint32_t m[4] = {0u, 0u, 0u, 0u};
+    for (int k = 0; k < kTierLevels; ++k) {
+      const int pos = ((1 << k) | (tid >> (4 - k))) - 1;
+      if (!((tid >> (3 - k)) & 1)) m[pos >> 2] |= 1u << ((pos & 3) * 8);
+    }
+    ts->lut[tid] = make_uint4(m[0], m[1], m[2], m[3]);
+  }
+  if constexpr (ADAPT) {
+    for (int i = tid; i < kHash; i += kBlock) ts->ht[i] = 0;
+  } else {
+    for (int i = tid; i < kSmap; i += kBlock) ts->smap[i] = (uint8_t)kNone;
+  }
+  for (int s = tid; s < kMaxSlots; s += kBlock) {
+    ts->key[s] = -1;
+    ts->stamp[s] = -1;
+    ts->lo[s] = ts->hi[s] = ts->dep[s] = 0;
+  }
+  if (tid < 3) ts->miss_n[tid] = 0;
+  if (tid < 3 * kWaves) ts->flag[tid / kWaves][tid % kWaves] = 0;
+  if (tid == 0) {
+    ts->reb_n = 0;
+    ts->key[0] = root;  // slot 0 holds tier 1 and is never replaced
+    ts->stamp[0] = 0x7fffffff;
+    ts->hi[0] = maxv;
+  }
+  __syncthreads();
+
+  // Tier-1 insertion mask of value v.
+  const uint4 lim1 = level_mask(stop < kTierLevels ? stop : kTierLevels);
+  auto mask1 = [&](int v) -> uint4 {
+    if constexpr (ADAPT)
+      return amask(topo, root, 0, stop, v);
+    else
+      return and4(ts->lut[(v >> (bits - kTierLevels)) & 15], lim1);
+  };
+
+  // ---- column trees (tier 1) of the segment's first window
+  for (int lc = tid; lc < ncols; lc += kBlock) {
+    const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
+    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+    for (int dz = -zr; dz <= zr; ++dz) {
+      const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+      for (int j = -r; j <= r; ++j) {
+        const int v = src[zz * a.sss + clampi(yb + j, a.h - 1) * a.srs + cx];
+        acc = add4(acc, mask1(v));
+      }
+    }
+    vec(slots, cp16, 0, lc) = acc;
+  }
+  // the padding columns past ncols are never read
+  __syncthreads();
+
+  const int lx = wv * 64 + lane;  // output x = x0 + lx; window columns lx+1 .. lx+span
+  const int64_t x = x0 + lx;
+  const uint32_t K = (uint32_t)a.rank;
+  const int maxcol = D3 ? span * span : span;  // largest column count
+  const int batch = 255 / maxcol > 0 ? 255 / maxcol : 1;
+  const int maxrounds = ADAPT ? (3 * bits) / kTierLevels + 1 : (stop + kTierLevels - 1) / kTierLevels;
+  int gr = 0;
+
+  for (int64_t y = yb; y < ye; ++y) {
+    // 2-D: fetch the values this row's column update will remove and insert now,
+    // so their latency overlaps the descent (a thread owns at most 2 columns)
+    int pre_o[2] = {0, 0}, pre_i[2] = {0, 0};
+    if (!D3 && y + 1 < ye) {
+      const int64_t yo = clampi(y - r, a.h - 1), yi = clampi(y + r + 1, a.h - 1);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int lc = tid + k * kBlock;
+        if (lc < ncols) {
+          const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
+          pre_o[k] = src[z * a.sss + yo * a.srs + cx];
+          pre_i[k] = src[z * a.sss + yi * a.srs + cx];
+        }
+      }
+    }
+    int node = root, lo = 0, hi = maxv, depth = 0;
+    uint32_t acc = 0;
+    bool done = (x >= a.w) || (stop == 0);
+    int res = 0;
+    int slot = 0;
+
+    for (int round = 0; round <= maxrounds; ++round) {
+      const bool act = !done;
+      const uint64_t pend = ballot(act && slot >= 0);
+      uint32_t W[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+      if (pend) {
+        // How many distinct subtrees do this wave's pixels need?
+        int groups = 0;
+        for (uint64_t t = pend; t && groups <= a.max_groups; ++groups)
+          t &= ~ballot(slot == readlane(slot, __builtin_ctzll(t)));
+        if (groups <= a.max_groups) {
+          for (uint64_t t = pend; t;) {
+            const int s = readlane(slot, __builtin_ctzll(t));
+            const uint64_t m = ballot(slot == s) & t;
+            t &= ~m;
+            coop_counts(W, slots, cp16, s, (m >> lane) & 1, lx, span, lane, wv * 64);
+          }
+        } else if (act && slot >= 0) {
+          direct_counts(W, slots, cp16, slot, lx, span, batch);
+        }
+      }
+      // Pixels whose subtree no slot holds: one scratch build per subtree.
+      for (uint64_t fb = ballot(act && slot < 0); fb;) {
+        const int leader = __builtin_ctzll(fb);
+        const int klo = readlane(lo, leader), khi = readlane(hi, leader);
+        const int kdep = readlane(depth, leader), knode = readlane(node, leader);
+        const uint64_t m = ballot(act && slot < 0 && lo == klo && depth == kdep) & fb;
+        fb &= ~m;
+        scratch_build<T, ADAPT, D3>(scr, src, a, ts, topo, x0 + wv * 64, y, z, lane, span, knode,
+                                    klo, khi, kdep);
+        wave_sync_lds();
+        if ((m >> lane) & 1) direct_counts(W, scr - (size_t)wv * 64 * 16, 0, 0, lx, span, batch);
+        wave_sync_lds();
+      }
+      // Descend (up to) the four levels of this tier.
+      if (act) {
+        int p = 1;
+#pragma unroll
+        for (int k = 0; k < kTierLevels; ++k) {
+          if (!done) {
+            int split, lch = 0, rch = 0;
+            bool lleaf, rleaf;
+            if constexpr (ADAPT) {
+              const TopoNode t = topo[node];
+              split = t.split;
+              lch = t.left;
+              rch = t.right;
+              lleaf = lch < 0;
+              rleaf = rch < 0;
+            } else {
+              split = lo + (1 << (bits - 1 - depth));
+              lleaf = rleaf = depth + 1 >= bits;
+            }
+            const uint32_t wl = wsel(W, p - 1);
+            const bool left = acc + wl > K;
+            bool leaf;
+            if (left) {
+              hi = split - 1;
+              node = lch;
+              leaf = lleaf;
+            } else {
+              acc += wl;
+              lo = split;
+              node = rch;
+              leaf = rleaf;
+            }
+            ++depth;
+            p = 2 * p + (left ? 0 : 1);
+            if (leaf || depth >= stop) {
+              done = true;
+              res = lo;
+            }
+          }
+        }
+      }
+      // Tier transition: pixels entering a deeper subtree look up its slot;
+      // subtrees no slot holds are queued as misses for thread 0.
+      const bool exited = !done;
+      const int key = exited ? (ADAPT ? node : ukey(depth, lo >> (bits - depth))) : 0;
+      const int b = gr % 3;
+      if (tid == 0) ts->miss_n[(gr + 1) % 3] = 0;
+      const uint64_t ex = ballot(exited);
+      if (lane == 0) ts->flag[b][wv] = ex != 0;
+      int newslot = -1;
+      for (uint64_t t = ex; t;) {
+        const int leader = __builtin_ctzll(t);
+        const int k = readlane(key, leader);
+        const uint64_t m = ballot(key == k) & t;
+        t &= ~m;
+        const int hs = ADAPT ? ht_find(ts->ht, k) : (ts->smap[k] == kNone ? -1 : ts->smap[k]);
+        if (hs >= 0) {
+          if (lane == leader) ts->stamp[hs] = (int)y;
+          if ((m >> lane) & 1) newslot = hs;
+        } else {
+          if (lane == leader) {
+            const int i = atomicAdd(&ts->miss_n[b], 1);
+            if (i < kMissCap) {
+              ts->miss[i][0] = k;
+              ts->miss[i][1] = lo;
+              ts->miss[i][2] = hi;
+              ts->miss[i][3] = depth;
+            }
+          }
+          if ((m >> lane) & 1) newslot = -2;
+        }
+      }
+      __syncthreads();
+      bool any = false;
+      for (int w2 = 0; w2 < kWaves; ++w2) any |= ts->flag[b][w2] != 0;
+      const int nmiss = ts->miss_n[b] < kMissCap ? ts->miss_n[b] : kMissCap;
+      ++gr;
+      if (!any) break;
+      if (nmiss > 0) {
+        if (tid == 0) assign_slots<ADAPT>(ts, nmiss, (int)y, a.nslots);
+        __syncthreads();
+        const int nreb = ts->reb_n;
+        if (nreb > 0) {
+          // Rebuild the new slots from the window's raw values (each thread
+          // owns its columns: no atomics, no barrier between clear and fill).
+          for (int lc = tid; lc < ncols; lc += kBlock) {
+            const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
+            for (int i = 0; i < nreb; ++i) {
+              const int rs = ts->reb[i][0], rkey = ts->reb[i][1], rlo = ts->reb[i][2];
+              const int rdep = ts->reb[i][3];
+              const int rhi = ts->hi[rs];
+              const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+              uint4 c = make_uint4(0u, 0u, 0u, 0u);
+              for (int dz = -zr; dz <= zr; ++dz) {
+                const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+#pragma unroll 4
+                for (int j = -r; j <= r; ++j) {
+                  const int v = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
+                  if (v >= rlo && v <= rhi) {
+                    if constexpr (ADAPT)
+                      c = add4(c, amask(topo, rkey, rdep, stop, v));
+                    else
+                      c = add4(c, and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim));
+                  }
+                }
+              }
+              vec(slots, cp16, rs, lc) = c;
+            }
+          }
+          __syncthreads();
+        }
+        if (exited && newslot == -2)
+          newslot = ADAPT ? ht_find(ts->ht, key) : (ts->smap[key] == kNone ? -1 : ts->smap[key]);
+      }
+      if (exited) slot = newslot;  // -1: no slot, count directly
+    }
+    if (x < a.w) dst[z * a.dss + y * a.drs + x] = (T)res;
+    __syncthreads();
+
+    // ---- next window: every column drops row y-r and takes row y+r+1
+    if (y + 1 < ye) {
+      const int64_t yo = clampi(y - r, a.h - 1), yi = clampi(y + r + 1, a.h - 1);
+      if (yo != yi) {
+        for (int lc = tid; lc < ncols; lc += kBlock) {
+          const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
+          for (int pass = 0; pass < 2; ++pass) {  // removals first, then insertions
+            const int64_t yy = pass == 0 ? yo : yi;
+            for (int dz = -zr; dz <= zr; ++dz) {
+              const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+              const int v = D3 ? (int)src[zz * a.sss + yy * a.srs + cx]
+                               : (pass == 0 ? pre_o[lc >= kBlock] : pre_i[lc >= kBlock]);
+              if constexpr (ADAPT) {
+                // walk down the tiers while their subtrees are held
+                int nd = root, s = 0, dep = 0;
+                for (int t = 0; t <= (3 * bits) / kTierLevels && nd >= 0 && dep < stop; ++t) {
+                  if (t > 0) {
+                    s = ht_find(ts->ht, nd);
+                    if (s < 0) break;
+                  }
+                  uint4& cv = vec(slots, cp16, s, lc);
+                  const uint4 m = amask(topo, nd, dep, stop, v);
+                  cv = pass == 0 ? sub4(cv, m) : add4(cv, m);
+                  for (int k = 0; k < kTierLevels && nd >= 0; ++k) {
+                    const TopoNode tn = topo[nd];
+                    nd = v < tn.split ? tn.left : tn.right;
+                  }
+                  dep += kTierLevels;
+                }
+              } else {
+                for (int t = 0; t < ntiers; ++t) {
+                  const int dep = t * kTierLevels;
+                  if (dep >= stop) break;
+                  int s = 0;
+                  if (t > 0) {
+                    s = ts->smap[ukey(dep, v >> (bits - dep))];
+                    if (s == (int)kNone) continue;
+                  }
+                  const uint4 m = and4(ts->lut[(v >> (bits - dep - kTierLevels)) & 15],
+                                       level_mask(stop - dep < kTierLevels ? stop - dep
+                                                                           : kTierLevels));
+                  uint4& cv = vec(slots, cp16, s, lc);
+                  cv = pass == 0 ? sub4(cv, m) : add4(cv, m);
+                }
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, bool ADAPT, bool D3>
+hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
+  auto kern = k_median_tiered<T, ADAPT, D3>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t grid = (int64_t)a.strips * a.segs * a.d;
+  hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(kBlock), lds, stream, a);
+  return hipGetLastError();
+}
+
+size_t align16_host(size_t b) { return (b + 15) & ~(size_t)15; }
+
+}  // namespace
+
+size_t tiered_meta_bytes(int r) {
+  return align16_host(sizeof(TierState)) + (size_t)kWaves * (64 + 2 * r + 1) * 16;
+}
+
+hipError_t launch_median_tiered(const MedianArgs& a, int bytes, int dims, bool adaptive,
+                                size_t lds, hipStream_t stream) {
+  const bool d3 = dims == 3;
+  if (bytes == 1) {
+    if (adaptive) return d3 ? launch_t<uint8_t, true, true>(a, lds, stream)
+                            : launch_t<uint8_t, true, false>(a, lds, stream);
+    return d3 ? launch_t<uint8_t, false, true>(a, lds, stream)
+              : launch_t<uint8_t, false, false>(a, lds, stream);
+  }
+  if (adaptive) return d3 ? launch_t<uint16_t, true, true>(a, lds, stream)
+                          : launch_t<uint16_t, true, false>(a, lds, stream);
+  return d3 ? launch_t<uint16_t, false, true>(a, lds, stream)
+            : launch_t<uint16_t, false, false>(a, lds, stream);
+}
+
+}  // namespace hrrm
