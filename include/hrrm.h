@@ -208,12 +208,19 @@ typedef struct {
   double t_done;
 } hrrm_result;
 
-/* Start a server on the context's device.  device_mem_budget bounds the bytes
- * of device memory held by admitted requests (input + output); max_inflight
- * bounds the number of admitted, unreleased requests; max_queue bounds the
- * host queue of not-yet-admitted requests. */
+/* Server flags. */
+#define HRRM_SERVER_PER_IMAGE 1u /* launch each admitted image on its own (comparison mode)
+                                    instead of one persistent batched launch per batch */
+
+/* Start a server on the context's device (the server copies the context's tile
+ * table and drives its own context from a worker thread; the caller's context
+ * stays usable).  device_mem_budget bytes of device memory are allocated once
+ * and hold the inputs and outputs of admitted requests; max_inflight bounds
+ * the admitted, unreleased requests; max_queue bounds the host queue of
+ * not-yet-admitted requests.  Requests are filtered with the PLAIN median.
+ * Errors: EINVAL, ENOMEM (budget not allocatable), EDEVICE. */
 int hrrm_server_create(hrrm_ctx ctx, size_t device_mem_budget, int32_t max_inflight,
-                       int32_t max_queue, hrrm_server* out);
+                       int32_t max_queue, uint32_t flags, hrrm_server* out);
 
 /* Queue a request (non-blocking; the input is read on admission, so it must
  * stay valid until hrrm_server_poll reports the ticket done).  EAGAIN if the

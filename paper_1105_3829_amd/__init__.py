@@ -91,7 +91,8 @@ def lib():
                 "hrrm_set_tile_config": ([vp, i32, i32, i32, i32, ctypes.POINTER(TileConfig)], i32),
                 "hrrm_get_tile_config": ([vp, i32, i32, i32, i32, i64, i64, i64,
                                           ctypes.POINTER(TileConfig)], i32),
-                "hrrm_server_create": ([vp, ctypes.c_size_t, i32, i32, ctypes.POINTER(vp)], i32),
+                "hrrm_server_create": ([vp, ctypes.c_size_t, i32, i32, ctypes.c_uint32,
+                                        ctypes.POINTER(vp)], i32),
                 "hrrm_server_submit": ([vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)],
                                        i32),
                 "hrrm_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_Result)], i32),
@@ -249,6 +250,96 @@ class Context:
 
     def load_tuning(self, path: str):
         check(lib().hrrm_load_tuning(self._h, path.encode()))
+
+
+def _hip():
+    """The HIP runtime library the process already uses (for raw copies only)."""
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = ctypes.CDLL("libamdhip64.so")
+        _hiplib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_int]
+        _hiplib.hipMemcpy.restype = ctypes.c_int
+    return _hiplib
+
+
+_hiplib = None
+
+
+class Server:
+    """Continuous-batching request loop on one device (hrrm_server_*).
+
+    submit() takes a HOST image (numpy array or CPU tensor, ideally pinned) and
+    returns a ticket; the image must stay alive until the ticket is done, so the
+    wrapper keeps a reference.  poll() returns None until done, then a dict with
+    the device output pointer and the server-clock timestamps."""
+
+    PER_IMAGE = 1
+
+    def __init__(self, ctx: "Context", budget_bytes: int, max_inflight: int = 1024,
+                 max_queue: int = 1 << 20, per_image: bool = False):
+        self._h = ctypes.c_void_p()
+        check(lib().hrrm_server_create(ctx.handle, budget_bytes, max_inflight, max_queue,
+                                       self.PER_IMAGE if per_image else 0, ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, img, r: int) -> int:
+        torch = _torch()
+        t = img if isinstance(img, torch.Tensor) else torch.from_numpy(img)
+        if t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError("submit takes a (H, W) image with contiguous rows")
+        req = _Request(t.data_ptr(), t.shape[1], t.shape[0], t.stride(0), _dtype_code(t), int(r))
+        tk = ctypes.c_uint64()
+        check(lib().hrrm_server_submit(self._h, ctypes.byref(req), ctypes.byref(tk)))
+        self._keep[tk.value] = t
+        return tk.value
+
+    def poll(self, ticket: int):
+        res = _Result()
+        rc = lib().hrrm_server_poll(self._h, ticket, ctypes.byref(res))
+        if rc == EAGAIN:
+            return None
+        check(rc)
+        self._keep.pop(ticket, None)
+        return {"d_dst": res.d_dst, "width": res.width, "height": res.height, "dtype": res.dtype,
+                "status": res.status, "t_submit": res.t_submit, "t_admit": res.t_admit,
+                "t_done": res.t_done}
+
+    def fetch(self, res) -> "object":
+        """Copy a done ticket's output to a new host tensor (marshalling only)."""
+        torch = _torch()
+        dt = torch.uint8 if res["dtype"] == U8 else torch.int16
+        out = torch.empty((res["height"], res["width"]), dtype=dt)
+        rc = _hip().hipMemcpy(out.data_ptr(), res["d_dst"], out.numel() * out.element_size(), 2)
+        if rc != 0:
+            raise HrrmError(EDEVICE, "hipMemcpy device to host failed (%d)" % rc)
+        return out if res["dtype"] == U8 else out.view(torch.uint16)
+
+    def release(self, ticket: int):
+        check(lib().hrrm_server_release(self._h, ticket))
+
+    def cancel(self, ticket: int) -> bool:
+        rc = lib().hrrm_server_cancel(self._h, ticket)
+        if rc == EAGAIN:
+            return False
+        check(rc)
+        self._keep.pop(ticket, None)
+        return True
+
+    def now(self) -> float:
+        return lib().hrrm_server_now(self._h)
+
+    def close(self):
+        if self._h:
+            lib().hrrm_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _contexts = {}

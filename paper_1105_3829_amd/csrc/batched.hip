@@ -1,14 +1,199 @@
-// Persistent batched kernel (many uneven images in one launch).
+// Host side of the persistent batched launch (hrrm_median2d_batched).
+//
+// Many uneven 2-D images (8- or 16-bit, any radius up to the batch limit) are
+// filtered by ONE launch of a persistent kernel whose workgroups pull tiles of
+// all images from a device work counter.  Per image the tile shape comes from
+// the context's tile table; the LDS of the launch is fixed, so each image gets
+// as many tier slots as fit next to its radius-dependent state.
+//
+// The launch (counter reset + persistent kernel) is captured once per stream
+// into a HIP graph and replayed; a batch only uploads its descriptors (into a
+// device buffer owned by that stream's entry) before the replay.  The counter
+// is reset by a kernel node, not a memset node.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
 #include "hrrm.h"
 #include "hrrm_ctx.h"
+#include "hrrm_internal.h"
 
 namespace hrrm {
-void Context::release_batch() {}
+
+namespace {
+constexpr int kBatchCap = 4096;           // images per batch
+constexpr size_t kBatchLds = 80 * 1024;   // dynamic LDS per workgroup: two workgroups per CU
+constexpr int kBatchMaxR = 127;
+}  // namespace
+
+constexpr size_t kDescOffset = 256;  // descriptors start here in the device buffer
+constexpr size_t kBatchBytes = kDescOffset + sizeof(BatchImage) * kBatchCap;
+
+BatchStream* Context::batch_for(hipStream_t s) {
+  for (auto& b : batch)
+    if (b.stream == s) return &b;
+  BatchStream b{};
+  b.stream = s;
+  if (hipMalloc(&b.d_buf, kBatchBytes) != hipSuccess) return nullptr;
+  if (hipHostMalloc(&b.h_stage, kBatchBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(b.d_buf);
+    return nullptr;
+  }
+  if (hipEventCreateWithFlags(&b.staged, hipEventDisableTiming) != hipSuccess) {
+    (void)hipFree(b.d_buf);
+    (void)hipHostFree(b.h_stage);
+    return nullptr;
+  }
+  batch.push_back(b);
+  return &batch.back();
+}
+
+void Context::release_batch() {
+  for (auto& b : batch) {
+    if (b.pending) (void)hipEventSynchronize(b.staged);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    if (b.staged) (void)hipEventDestroy(b.staged);
+    if (b.d_buf) (void)hipFree(b.d_buf);
+    if (b.h_stage) (void)hipHostFree(b.h_stage);
+  }
+  batch.clear();
+}
+
+int batched_grid(int device) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return cus * 2;
+}
+
+int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t stream,
+                bool use_graph) {
+  std::vector<BatchImage> descs;
+  descs.reserve(count);
+  int64_t tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    const hrrm_image& im = images[i];
+    int rc = validate(im.src, im.dst, im.dtype, im.width, im.height, 1, im.src_row_stride, 0,
+                      im.dst_row_stride, 0, im.r, 2);
+    if (rc != HRRM_OK) return fail(rc, "image %d: %s", i, hrrm_last_error());
+    if (im.r > kBatchMaxR) return fail(HRRM_EUNSUPPORTED, "image %d: radius %d", i, im.r);
+    if (im.width == 0 || im.height == 0) continue;
+    const int bytes = im.dtype == HRRM_U8 ? 1 : 2;
+    const TileConfig t = ctx->tile_for(bytes, 2, im.r, false, im.width, im.height, 1);
+    BatchImage b{};
+    MedianArgs& a = b.args;
+    a.src = im.src;
+    a.dst = im.dst;
+    a.w = im.width;
+    a.h = im.height;
+    a.d = 1;
+    a.srs = im.src_row_stride;
+    a.drs = im.dst_row_stride;
+    a.r = im.r;
+    a.rank = ((int64_t)(2 * im.r + 1) * (2 * im.r + 1) - 1) / 2;
+    a.bits = 8 * bytes;
+    a.stop = a.bits;
+    a.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(t.seg_rows, im.height));
+    a.strips = (int32_t)((im.width + kBlock - 1) / kBlock);
+    a.segs = (int32_t)((im.height + a.seg_rows - 1) / a.seg_rows);
+    a.ncols = kBlock + 2 * im.r + 1;
+    a.cp = (a.ncols + 3) & ~3;
+    const size_t meta = tiered_meta_bytes(im.r) + 16;
+    const size_t slot_bytes = (size_t)a.cp * 16;
+    int ns = kBatchLds > meta ? (int)((kBatchLds - meta) / slot_bytes) : 0;
+    if (t.nslots > 0) ns = std::min(ns, t.nslots);
+    ns = std::min(ns, kMaxSlots);
+    if (ns < 1) return fail(HRRM_EUNSUPPORTED, "image %d: radius %d does not fit a batch", i, im.r);
+    a.nslots = ns;
+    a.min_group = std::max(1, t.min_group);
+    a.max_groups = std::max(0, t.max_groups);
+    tiles += (int64_t)a.strips * a.segs;
+    if (tiles > 0x7fffffff) return fail(HRRM_EUNSUPPORTED, "batch has too many tiles");
+    b.tile_end = tiles;
+    b.bytes = bytes;
+    descs.push_back(b);
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  if (descs.empty()) return HRRM_OK;
+  BatchStream* bs = ctx->batch_for(stream);
+  if (!bs) return fail(HRRM_ENOMEM, "batch descriptor buffers");
+  // device buffer: work counter at byte 0, image count at byte 64, descriptors
+  // from kDescOffset; uploaded from the pinned staging copy once the previous
+  // upload from it has completed
+  uint32_t* d_counter = (uint32_t*)bs->d_buf;
+  int32_t* d_hdr = (int32_t*)((char*)bs->d_buf + 64);
+  const BatchImage* d_imgs = (const BatchImage*)((char*)bs->d_buf + kDescOffset);
+  if (bs->pending) {
+    e = hipEventSynchronize(bs->staged);
+    if (e != hipSuccess) return fail_hip(e, "batch staging wait");
+    bs->pending = false;
+  }
+  const int32_t n = (int32_t)descs.size();
+  char* stage = (char*)bs->h_stage;
+  std::memcpy(stage + 64, &n, sizeof n);
+  std::memcpy(stage + kDescOffset, descs.data(), sizeof(BatchImage) * descs.size());
+  e = hipMemcpyAsync((char*)bs->d_buf + 64, stage + 64,
+                     kDescOffset - 64 + sizeof(BatchImage) * descs.size(), hipMemcpyHostToDevice,
+                     stream);
+  if (e != hipSuccess) return fail_hip(e, "batch descriptor upload");
+  e = hipEventRecord(bs->staged, stream);
+  if (e != hipSuccess) return fail_hip(e, "batch staging event");
+  bs->pending = true;
+  const int grid = batched_grid(ctx->device);
+  if (!use_graph || stream == nullptr) {
+    e = launch_batched_prepare(kBatchLds);
+    if (e != hipSuccess) return fail_hip(e, "batched kernel attribute");
+    e = launch_batched(d_imgs, d_hdr, d_counter, grid, kBatchLds, stream);
+    if (e != hipSuccess) return fail_hip(e, "batched launch");
+    return HRRM_OK;
+  }
+  if (!bs->exec) {
+    // configure the kernel once outside capture, then capture the launch pair
+    e = launch_batched_prepare(kBatchLds);
+    if (e != hipSuccess) return fail_hip(e, "batched kernel attribute");
+    e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
+    hipError_t le = launch_batched(d_imgs, d_hdr, d_counter, grid, kBatchLds, stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(stream, &g);
+    if (le != hipSuccess) return fail_hip(le, "batched launch (capture)");
+    if (e != hipSuccess) return fail_hip(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail_hip(e, "hipGraphInstantiate");
+    }
+    bs->graph = g;
+    bs->exec = x;
+  }
+  e = hipGraphLaunch(bs->exec, stream);
+  if (e != hipSuccess) return fail_hip(e, "hipGraphLaunch");
+  return HRRM_OK;
+}
+
 }  // namespace hrrm
 
+using namespace hrrm;
+
 extern "C" {
-int32_t hrrm_batch_capacity(void) { return 0; }
-int hrrm_median2d_batched(hrrm_ctx, const hrrm_image*, int32_t, void*) {
-  return hrrm::fail(HRRM_EUNSUPPORTED, "batched launch not built yet");
+
+int32_t hrrm_batch_capacity(void) { return kBatchCap; }
+
+int hrrm_median2d_batched(hrrm_ctx ctx, const hrrm_image* images, int32_t count,
+                          void* hip_stream) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  if (count < 0 || count > kBatchCap)
+    return fail(HRRM_EINVAL, "batch count %d outside 0..%d", count, kBatchCap);
+  if (count > 0 && !images) return fail(HRRM_EINVAL, "null image array");
+  return run_batched(c, images, count, (hipStream_t)hip_stream, true);
 }
-}
+
+}  // extern "C"

@@ -4,6 +4,7 @@
 
 #include <vector>
 
+#include "hrrm.h"
 #include "hrrm_internal.h"
 
 namespace hrrm {
@@ -12,6 +13,18 @@ struct TunedEntry {
   int bytes, dims, r, adaptive;
   TileConfig cfg;
   double ms;
+};
+
+// Per-stream state of batched launches: descriptor buffer, work counter and
+// the captured graph of the launch.
+struct BatchStream {
+  hipStream_t stream;
+  void* d_buf;        // header (image count at byte 64) + descriptors at byte 256
+  void* h_stage;      // pinned staging copy of d_buf's upload
+  hipEvent_t staged;  // recorded after the upload; the staging copy is reused after it
+  bool pending;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
 };
 
 struct Context {
@@ -24,20 +37,14 @@ struct Context {
   bool capture_locked = false;
   std::vector<TunedEntry> tuned;
 
-  // batched launches (persistent kernel)
-  void* batch_desc = nullptr;   // device descriptor ring
-  void* batch_host = nullptr;   // pinned staging copy
-  void* batch_ctrl = nullptr;   // device work counters
-  int batch_cap = 0;
-  hipGraphExec_t batch_exec = nullptr;
-  hipGraph_t batch_graph = nullptr;
-  hipStream_t batch_stream = nullptr;
-  int batch_grid = 0;
+  // batched launches (persistent kernel), one entry per stream used
+  std::vector<BatchStream> batch;
 
   TileConfig tile_for(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
                       int64_t d) const;
   int ensure_topology(int bytes, int64_t pixels);
   void release_batch();
+  BatchStream* batch_for(hipStream_t s);
   ~Context();
 };
 
@@ -47,6 +54,8 @@ void clear_error();
 TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h, int64_t d);
 int validate(const void* src, const void* dst, int dtype, int64_t w, int64_t h, int64_t d,
              int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r, int dims);
+int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t stream,
+                bool use_graph);
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
                int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,
                int64_t rank, int drop, int variant, int dims, hipStream_t stream,

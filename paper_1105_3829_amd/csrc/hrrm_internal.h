@@ -41,6 +41,15 @@ struct MedianArgs {
   const TopoNode* topo;  // adaptive topology (device), else null
 };
 
+// One image of a persistent batched launch: its launch arguments, element size
+// and the exclusive end of its range in the batch's tile index space.
+struct BatchImage {
+  MedianArgs args;
+  int64_t tile_end;
+  int32_t bytes;
+  int32_t pad;
+};
+
 // Tile shape / strategy of one launch.
 struct TileConfig {
   int32_t seg_rows;
@@ -58,6 +67,16 @@ hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive
 
 // LDS bytes a launch with these parameters needs.
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);
+
+// Tiered-kernel LDS bytes besides the slots, for radius r.
+size_t tiered_meta_bytes(int r);
+
+// Persistent batched launch (zeroes *d_counter first, then runs `grid`
+// workgroups over all tiles of the images in d_imgs; d_hdr[0] = image count).
+// launch_batched_prepare sets the kernel's LDS limit; call it before capture.
+hipError_t launch_batched_prepare(size_t lds);
+hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32_t* d_counter,
+                          int grid, size_t lds, hipStream_t stream);
 
 // Adaptive topology pre-pass (Sec. III-C).  Builds `topo` (2^bits - 1 nodes)
 // from the input's global histogram mixed 1:1 with the histogram of its

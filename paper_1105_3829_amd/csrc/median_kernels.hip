@@ -279,7 +279,6 @@ hipError_t launch_dense(const MedianArgs& a, size_t lds, hipStream_t stream) {
 
 }  // namespace
 
-size_t tiered_meta_bytes(int r);
 hipError_t launch_median_tiered(const MedianArgs& a, int bytes, int dims, bool adaptive,
                                 size_t lds, hipStream_t stream);
 

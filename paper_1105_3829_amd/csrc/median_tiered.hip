@@ -312,9 +312,12 @@ __device__ void assign_slots(TierState* ts, int nmiss, int stamp, int nslots) {
   ts->reb_n = nreb;
 }
 
+// One workgroup tile: output columns [strip*256, strip*256 + 256) of rows
+// [seg*seg_rows, seg*seg_rows + seg_rows) of slice z.  `lds` is the dynamic LDS
+// of the workgroup (slots, tier state, per-wave scratch).
 template <typename T, bool ADAPT, bool D3>
-__global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
-  extern __shared__ __align__(16) uint8_t lds[];
+__device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int strip, int seg,
+                                          int64_t z) {
   const T* __restrict__ src = (const T*)a.src;
   T* __restrict__ dst = (T*)a.dst;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -324,11 +327,6 @@ __global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
   const size_t cp16 = (size_t)a.cp * 16;  // bytes of one slot (cp >= ncols columns)
   const TopoNode* __restrict__ topo = a.topo;
 
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int strip = bid % a.strips;
-  const int rest = bid / a.strips;
-  const int seg = rest % a.segs;
-  const int64_t z = rest / a.segs;
   const int64_t x0 = (int64_t)strip * kBlock;
   const int64_t yb = (int64_t)seg * a.seg_rows;
   const int64_t ye = yb + a.seg_rows < a.h ? yb + a.seg_rows : a.h;
@@ -633,6 +631,54 @@ __global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
 }
 
 template <typename T, bool ADAPT, bool D3>
+__global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int rest = bid / a.strips;
+  tile_body<T, ADAPT, D3>(a, lds, bid % a.strips, rest % a.segs, rest / a.segs);
+}
+
+// Persistent batched launch: every workgroup repeatedly takes the next tile
+// index from a device counter and runs the tile body for whichever image the
+// tile belongs to (plain 2-D median, 8- or 16-bit).  Tiles of one image are
+// contiguous in the index space, images in descriptor order.
+__global__ __launch_bounds__(kBlock) void k_median_batched(const BatchImage* __restrict__ imgs,
+                                                           const int32_t* __restrict__ hdr,
+                                                           uint32_t* __restrict__ counter) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ int s_tile;
+  const int n = hdr[0];
+  const int64_t total = n > 0 ? imgs[n - 1].tile_end : 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();  // every thread has read s_tile before thread 0 overwrites it
+    if (t >= total) break;
+    int lo = 0, hi = n - 1;  // first image whose tile range ends after t
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (imgs[mid].tile_end > t)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const BatchImage& bi = imgs[lo];
+    const int64_t local = t - (bi.tile_end - (int64_t)bi.args.strips * bi.args.segs);
+    const int strip = (int)(local % bi.args.strips), seg = (int)(local / bi.args.strips);
+    if (bi.bytes == 1)
+      tile_body<uint8_t, false, false>(bi.args, lds, strip, seg, 0);
+    else
+      tile_body<uint16_t, false, false>(bi.args, lds, strip, seg, 0);
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+__global__ void k_zero_counter(uint32_t* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+template <typename T, bool ADAPT, bool D3>
 hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
   auto kern = k_median_tiered<T, ADAPT, D3>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -646,6 +692,19 @@ hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
 size_t align16_host(size_t b) { return (b + 15) & ~(size_t)15; }
 
 }  // namespace
+
+hipError_t launch_batched_prepare(size_t lds) {
+  return hipFuncSetAttribute((const void*)k_median_batched,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32_t* d_counter,
+                          int grid, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, d_counter);
+  hipLaunchKernelGGL(k_median_batched, dim3(grid), dim3(kBlock), lds, stream, d_imgs, d_hdr,
+                     d_counter);
+  return hipGetLastError();
+}
 
 size_t tiered_meta_bytes(int r) {
   return align16_host(sizeof(TierState)) + (size_t)kWaves * (64 + 2 * r + 1) * 16;

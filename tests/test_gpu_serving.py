@@ -1,0 +1,168 @@
+"""Batched persistent launch and the continuous-batching server on the GPU.
+
+Every output must be bit-identical to the oracle (small images) and to the
+same image filtered alone by hrrm_median2d (tolerance 0)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import announce, first_mismatch, to_dev, to_host
+from paper_1105_3829_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hrrm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1105_3829_amd as m
+    m.lib()
+    return m
+
+
+def _mixed_images(seed, n, max_side=300):
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        h = int(g.integers(1, max_side))
+        w = int(g.integers(1, max_side))
+        r = int(g.choice([0, 1, 2, 3, 7, 15, 31]))
+        if g.integers(0, 2):
+            img = datagen.uniform_u8(h, w, seed=seed * 100 + i)
+        else:
+            img = datagen.xray_u16(h, w, seed=seed * 100 + i)
+        out.append((img, r))
+    return out
+
+
+@pytest.mark.parametrize("use_stream", [False, True])
+def test_batched_matches_oracle(hrrm, use_stream):
+    import torch
+    ctx = hrrm.Context(0)
+    stream = torch.cuda.Stream() if use_stream else None
+    for rep in range(3):  # graph replays with different batches
+        imgs = _mixed_images(10 * rep + int(use_stream), 12)
+        announce("batched", "stream" if use_stream else "default", rep,
+                 [(i.shape, i.dtype.name, r) for i, r in imgs])
+        srcs = [to_dev(i) for i, _ in imgs]
+        outs = [torch.empty_like(s) for s in srcs]
+        torch.cuda.synchronize()  # inputs were written on the default stream
+        ctx.median2d_batched(srcs, [r for _, r in imgs], outs=outs, stream=stream)
+        torch.cuda.synchronize()
+        for (img, r), o in zip(imgs, outs):
+            got = to_host(o)
+            want = oracle.median2d(img, r)
+            assert np.array_equal(got, want), (img.shape, r, first_mismatch(got, want))
+
+
+def test_batched_large_mix_equals_alone(hrrm):
+    import torch
+    ctx = hrrm.Context(0)
+    g = np.random.default_rng(5)
+    imgs = []
+    for i in range(20):
+        h, w = int(g.integers(256, 1200)), int(g.integers(256, 1200))
+        r = int(g.choice([1, 2, 3, 7, 15, 31]))
+        img = datagen.uniform_u8(h, w, seed=i) if i % 2 else datagen.xray_u16(h, w, seed=i)
+        imgs.append((img, r))
+    srcs = [to_dev(i) for i, _ in imgs]
+    outs = [torch.empty_like(s) for s in srcs]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    ctx.median2d_batched(srcs, [r for _, r in imgs], outs=outs, stream=stream)
+    torch.cuda.synchronize()
+    for (img, r), s, o in zip(imgs, srcs, outs):
+        alone = to_host(ctx.median2d(s, r))
+        assert np.array_equal(to_host(o), alone), (img.shape, r)
+    # sampled oracle check on the largest image
+    k = max(range(len(imgs)), key=lambda i: imgs[i][0].size)
+    img, r = imgs[k]
+    ys = g.integers(0, img.shape[0], 2000)
+    xs = g.integers(0, img.shape[1], 2000)
+    assert np.array_equal(to_host(outs[k])[ys, xs], oracle.rank2d_at(img, r, xs, ys))
+
+
+def test_batched_rejects_bad_image(hrrm):
+    import torch
+    ctx = hrrm.Context(0)
+    a = to_dev(datagen.uniform_u8(10, 10))
+    with pytest.raises(hrrm.HrrmError):
+        ctx.median2d_batched([a], [200])
+    with pytest.raises(hrrm.HrrmError):
+        ctx.median2d_batched([a], [-1])
+
+
+def _run_server(hrrm, imgs, per_image=False, budget=1 << 30):
+    ctx = hrrm.Context(0)
+    srv = hrrm.Server(ctx, budget, per_image=per_image)
+    tickets = [srv.submit(img, r) for img, r in imgs]
+    outs = {}
+    deadline = time.time() + 60
+    while len(outs) < len(tickets):
+        for t in tickets:
+            if t in outs:
+                continue
+            res = srv.poll(t)
+            if res is not None:
+                assert res["status"] == 0
+                assert res["t_submit"] <= res["t_admit"] <= res["t_done"]
+                outs[t] = srv.fetch(res).numpy()
+                srv.release(t)
+        assert time.time() < deadline, "server did not finish"
+        time.sleep(0.001)
+    srv.close()
+    return [outs[t] for t in tickets]
+
+
+@pytest.mark.parametrize("per_image", [False, True])
+def test_server_results_mix_equal_alone(hrrm, per_image):
+    imgs = _mixed_images(7 + int(per_image), 40)
+    announce("server", "per-image" if per_image else "batched", len(imgs))
+    got = _run_server(hrrm, imgs, per_image)
+    ctx = hrrm.Context(0)
+    for (img, r), o in zip(imgs, got):
+        alone = to_host(ctx.median2d(to_dev(img), r))
+        assert np.array_equal(o, alone), (img.shape, r)
+        assert np.array_equal(o, oracle.median2d(img, r)), (img.shape, r)
+
+
+def test_server_small_budget_admits_in_turn(hrrm):
+    # a budget that holds only a couple of requests at once: later requests wait
+    # for earlier outputs to be released, and everything still completes
+    imgs = [(datagen.xray_u16(400, 500, seed=i), 5) for i in range(8)]
+    got = _run_server(hrrm, imgs, budget=2 * 2 * 400 * 512 * 2 + 4096)
+    for (img, r), o in zip(imgs, got):
+        assert np.array_equal(o, oracle.median2d(img, r))
+
+
+def test_server_errors_and_cancel(hrrm):
+    ctx = hrrm.Context(0)
+    srv = hrrm.Server(ctx, 1 << 20, max_inflight=1, max_queue=2)
+    big = datagen.uniform_u8(1024, 1024)
+    with pytest.raises(hrrm.HrrmError) as e:
+        srv.submit(big, 1)  # input + output exceed the budget: can never fit
+    assert e.value.code == hrrm.ENOMEM
+    small = datagen.uniform_u8(64, 64)
+    t1 = srv.submit(small, 1)
+    t2 = srv.submit(small, 1)
+    t3 = None
+    try:
+        t3 = srv.submit(small, 1)
+    except hrrm.HrrmError as err:
+        assert err.code == hrrm.EAGAIN  # queue of 2 is full (unless t1 was admitted already)
+    # with max_inflight = 1, t2 waits until t1 is released: it can be cancelled
+    while srv.poll(t1) is None:
+        time.sleep(0.001)
+    assert srv.cancel(t2) is True
+    srv.release(t1)
+    if t3 is not None:
+        while srv.poll(t3) is None:
+            time.sleep(0.001)
+        srv.release(t3)
+    with pytest.raises(hrrm.HrrmError):
+        srv.poll(t2)  # cancelled tickets are gone
+    srv.close()
