@@ -161,9 +161,12 @@ int32_t hrrm_batch_capacity(void);
  *                groups sum their 2r+1 column counters directly
  *   max_groups : cooperative groups per level before the rest count directly
  *   lds_budget : LDS bytes one workgroup may use (caps nslots; sets occupancy)
- *   tiered_u8  : 1 = 8-bit data also uses tiered storage (else dense) */
+ *   tiered_u8  : 1 = 8-bit data uses tiered storage (the default), 0 = dense
+ *   raw_window : windows of at most this many values ((2r+1)^D) count the
+ *                deeper tiers of the tree directly from the window's values
+ *                instead of holding them in slots */
 typedef struct {
-  int32_t seg_rows, nslots, min_group, max_groups, lds_budget, tiered_u8;
+  int32_t seg_rows, nslots, min_group, max_groups, lds_budget, tiered_u8, raw_window;
 } hrrm_tile_config;
 
 /* Set (cfg != NULL) or clear (cfg == NULL) the context's tile configuration
@@ -176,21 +179,34 @@ int hrrm_get_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
                          hrrm_variant variant, int64_t width, int64_t height, int64_t depth,
                          hrrm_tile_config* out);
 
-/* Time the tile candidates for (dtype, r, variant) on a synthetic image of
- * width x height drawn on the device, keep the fastest in the context's tile
- * table, and return its index in *best (may be NULL).  Synchronises the
- * context's device.  If cache_path is not NULL the table is also written there
- * (JSON).  hrrm_load_tuning reads such a file back. */
-int hrrm_autotune(hrrm_ctx ctx, hrrm_dtype dtype, int32_t r, hrrm_variant variant,
-                  int64_t width, int64_t height, const char* cache_path, int32_t* best);
+/* Autotune the 2-D tile configuration of one key (dtype, r, variant): time
+ * candidate configurations (segment height, LDS budget, cooperative-group
+ * policy, 8-bit storage) on a sample image by coordinate descent and keep the
+ * fastest in the context's tile table, which every later call (batched
+ * launches included) uses.  d_sample: a DEVICE image of width x height with
+ * row_stride (elements) to tune on, or NULL for a synthetic sample drawn on
+ * the device (uniform 8-bit values; 12-bit X-ray-like values for 16-bit).
+ * Every candidate's output is checked against the default configuration's on
+ * the device; EDEVICE if one ever differs.  Synchronises the device.  If
+ * cache_path is not NULL the whole tile table is written there (JSON, one
+ * entry per line).  *tried (may be NULL) receives the number of candidates
+ * timed.  A context created while the environment variable HRRM_TUNE_CACHE
+ * names a readable file starts from that table. */
+int hrrm_autotune(hrrm_ctx ctx, const void* d_sample, hrrm_dtype dtype, int32_t r,
+                  hrrm_variant variant, int64_t width, int64_t height, int64_t row_stride,
+                  const char* cache_path, int32_t* tried);
+
+/* Merge / write the context's tile table from / to a JSON cache file. */
 int hrrm_load_tuning(hrrm_ctx ctx, const char* cache_path);
+int hrrm_save_tuning(hrrm_ctx ctx, const char* cache_path);
 
 /* ---- Serving: continuous-batching request loop ---------------------------- */
 
 typedef struct hrrm_server_s* hrrm_server;
 
 typedef struct {
-  const void* src;        /* HOST pointer to the input (copied on admission) */
+  const void* src;        /* HOST pointer to the input (copied on admission; pinned memory with
+                             packed rows, src_row_stride == width, uploads at full link speed) */
   int64_t width, height;  /* pixels */
   int64_t src_row_stride; /* elements */
   int32_t dtype;          /* hrrm_dtype */
@@ -230,6 +246,11 @@ int hrrm_server_submit(hrrm_server srv, const hrrm_request* req, uint64_t* ticke
 
 /* HRRM_OK with *res filled once the ticket is done; EAGAIN before. */
 int hrrm_server_poll(hrrm_server srv, uint64_t ticket, hrrm_result* res);
+
+/* Report up to `max` done tickets not reported before, in completion order:
+ * tickets[i] and results[i] are filled; returns the number reported (>= 0).
+ * A ticket is reported once (by drain; poll may still be used on it). */
+int hrrm_server_drain(hrrm_server srv, uint64_t* tickets, hrrm_result* results, int32_t max);
 
 /* Give the output buffer of a done ticket back to the server. */
 int hrrm_server_release(hrrm_server srv, uint64_t ticket);

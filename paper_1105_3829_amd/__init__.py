@@ -47,7 +47,8 @@ class _Image(ctypes.Structure):
 class TileConfig(ctypes.Structure):
     _fields_ = [("seg_rows", ctypes.c_int32), ("nslots", ctypes.c_int32),
                 ("min_group", ctypes.c_int32), ("max_groups", ctypes.c_int32),
-                ("lds_budget", ctypes.c_int32), ("tiered_u8", ctypes.c_int32)]
+                ("lds_budget", ctypes.c_int32), ("tiered_u8", ctypes.c_int32),
+                ("raw_window", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,8 +87,10 @@ def lib():
                 "hrrm_rank2d": ([vp, vp, vp, i32, i64, i64, i64, i64, i32, i64, i32, i32, vp], i32),
                 "hrrm_median2d_batched": ([vp, ctypes.POINTER(_Image), i32, vp], i32),
                 "hrrm_batch_capacity": ([], i32),
-                "hrrm_autotune": ([vp, i32, i32, i32, i64, i64, cp, ctypes.POINTER(i32)], i32),
+                "hrrm_autotune": ([vp, vp, i32, i32, i32, i64, i64, i64, cp, ctypes.POINTER(i32)],
+                                  i32),
                 "hrrm_load_tuning": ([vp, cp], i32),
+                "hrrm_save_tuning": ([vp, cp], i32),
                 "hrrm_set_tile_config": ([vp, i32, i32, i32, i32, ctypes.POINTER(TileConfig)], i32),
                 "hrrm_get_tile_config": ([vp, i32, i32, i32, i32, i64, i64, i64,
                                           ctypes.POINTER(TileConfig)], i32),
@@ -97,6 +100,8 @@ def lib():
                                        i32),
                 "hrrm_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(_Result)], i32),
                 "hrrm_server_release": ([vp, ctypes.c_uint64], i32),
+                "hrrm_server_drain": ([vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_Result),
+                                       i32], i32),
                 "hrrm_server_cancel": ([vp, ctypes.c_uint64], i32),
                 "hrrm_server_now": ([vp], ctypes.c_double),
                 "hrrm_server_destroy": ([vp], i32),
@@ -225,11 +230,22 @@ class Context:
         return outs
 
     def autotune(self, dtype: int, r: int, variant="plain", width: int = 4096, height: int = 4096,
-                 cache_path: Optional[str] = None) -> int:
-        best = ctypes.c_int32(-1)
-        check(lib().hrrm_autotune(self._h, dtype, r, _variant_code(variant), width, height,
-                                  cache_path.encode() if cache_path else None, ctypes.byref(best)))
-        return best.value
+                 sample=None, cache_path: Optional[str] = None) -> int:
+        """Tune the tile configuration for (dtype, r, variant); `sample` is an
+        optional (H, W) device tensor to tune on.  Returns candidates timed."""
+        tried = ctypes.c_int32(-1)
+        if sample is not None:
+            height, width = sample.shape
+            ptr, stride = sample.data_ptr(), sample.stride(0)
+        else:
+            ptr, stride = None, width
+        check(lib().hrrm_autotune(self._h, ptr, dtype, r, _variant_code(variant), width, height,
+                                  stride, cache_path.encode() if cache_path else None,
+                                  ctypes.byref(tried)))
+        return tried.value
+
+    def save_tuning(self, path: str):
+        check(lib().hrrm_save_tuning(self._h, path.encode()))
 
     def set_tile(self, dtype: int, dims: int, r: int, variant="plain", cfg=None, **fields):
         """Set the tile configuration for one key (cfg=None and no fields: reset)."""
@@ -315,6 +331,20 @@ class Server:
             raise HrrmError(EDEVICE, "hipMemcpy device to host failed (%d)" % rc)
         return out if res["dtype"] == U8 else out.view(torch.uint16)
 
+    def drain(self, max_n: int = 4096):
+        """Done tickets not reported before: list of (ticket, result dict)."""
+        tk = (ctypes.c_uint64 * max_n)()
+        rs = (_Result * max_n)()
+        n = check(lib().hrrm_server_drain(self._h, tk, rs, max_n))
+        out = []
+        for i in range(n):
+            r = rs[i]
+            self._keep.pop(tk[i], None)
+            out.append((tk[i], {"d_dst": r.d_dst, "width": r.width, "height": r.height,
+                                "dtype": r.dtype, "status": r.status, "t_submit": r.t_submit,
+                                "t_admit": r.t_admit, "t_done": r.t_done}))
+        return out
+
     def release(self, ticket: int):
         check(lib().hrrm_server_release(self._h, ticket))
 
@@ -380,8 +410,10 @@ def median2d_batched(srcs, radii, outs=None, stream=None):
 EXPORTED_SYMBOLS: List[str] = [
     "hrrm_last_error", "hrrm_version", "hrrm_ctx_create", "hrrm_ctx_destroy", "hrrm_ctx_reserve",
     "hrrm_median2d", "hrrm_median3d", "hrrm_rank2d", "hrrm_median2d_batched",
-    "hrrm_batch_capacity", "hrrm_autotune", "hrrm_load_tuning", "hrrm_set_tile_config",
+    "hrrm_batch_capacity", "hrrm_autotune", "hrrm_load_tuning", "hrrm_save_tuning",
+    "hrrm_set_tile_config",
     "hrrm_get_tile_config", "hrrm_server_create",
-    "hrrm_server_submit", "hrrm_server_poll", "hrrm_server_release", "hrrm_server_cancel",
+    "hrrm_server_submit", "hrrm_server_poll", "hrrm_server_drain", "hrrm_server_release",
+    "hrrm_server_cancel",
     "hrrm_server_now", "hrrm_server_destroy",
 ]

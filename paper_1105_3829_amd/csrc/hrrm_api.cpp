@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -44,7 +45,8 @@ const char* last_error() { return g_err.c_str(); }
 TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
                         int64_t d) {
   TileConfig t{};
-  const bool tiered = bytes == 2;
+  t.tiered_u8 = 1;  // the radix-16 tiered kernel is also the faster one for 8-bit data
+  const bool tiered = true;
   const int span = 2 * r + 1;
   t.min_group = 2;
   // tiered storage: the wave's window counts of one tier come from cooperative
@@ -52,9 +54,10 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   // or from per-lane sums over the 2r+1 columns (about 6.5 per column); take the
   // prefix sums while they are cheaper
   t.max_groups = tiered ? std::max(1, (int)((6.5 * span + 40) / 170)) : 64;
+  (void)bytes;
   t.nslots = 0;
-  t.tiered_u8 = 0;
   t.lds_budget = 80 * 1024;
+  t.raw_window = 49;  // r <= 3 (2-D) and r = 1 (3-D): deeper tiers counted raw
   // Enough workgroups to fill 256 CUs several times over, while keeping the
   // per-segment start-up (2r+1 rows inserted per column) small against the
   // rows a segment produces.
@@ -155,6 +158,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   a.cp = (a.ncols + 3) & ~3;
   a.min_group = std::max(1, t.min_group);
   a.max_groups = std::max(0, t.max_groups);
+  a.raw_window = std::max(0, t.raw_window);
   a.topo = nullptr;
 
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;
@@ -246,6 +250,12 @@ int hrrm_ctx_create(int device, hrrm_ctx* out) {
   Context* c = new (std::nothrow) Context();
   if (!c) return fail(HRRM_ENOMEM, "out of host memory");
   c->device = device;
+  if (const char* tc = getenv("HRRM_TUNE_CACHE")) {
+    if (FILE* f = fopen(tc, "r")) {
+      fclose(f);
+      (void)load_tuning(c, tc);
+    }
+  }
   *out = reinterpret_cast<hrrm_ctx>(c);
   return HRRM_OK;
 }
@@ -322,7 +332,8 @@ int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype
 static bool tile_ok(const hrrm_tile_config* c) {
   return c->seg_rows >= 1 && c->nslots >= 0 && c->nslots <= kMaxSlots && c->min_group >= 1 &&
          c->min_group <= 65 && c->max_groups >= 0 && c->lds_budget >= 16 * 1024 &&
-         c->lds_budget <= kLdsLimit && (c->tiered_u8 == 0 || c->tiered_u8 == 1);
+         c->lds_budget <= kLdsLimit && (c->tiered_u8 == 0 || c->tiered_u8 == 1) &&
+         c->raw_window >= 0;
 }
 
 int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
@@ -342,7 +353,8 @@ int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
           }), v.end());
   if (cfg) {
     TunedEntry e{bytes, dims, r, ad, TileConfig{cfg->seg_rows, cfg->nslots, cfg->min_group,
-                                                cfg->max_groups, cfg->lds_budget, cfg->tiered_u8},
+                                                cfg->max_groups, cfg->lds_budget, cfg->tiered_u8,
+                                                cfg->raw_window},
                  0.0};
     v.push_back(e);
   }
@@ -360,7 +372,7 @@ int hrrm_get_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
   const TileConfig t = c->tile_for(dtype == HRRM_U8 ? 1 : 2, dims, r, variant == HRRM_ADAPTIVE,
                                    width, height, dims == 3 ? depth : 1);
   *out = hrrm_tile_config{t.seg_rows, t.nslots, t.min_group, t.max_groups, t.lds_budget,
-                          t.tiered_u8};
+                          t.tiered_u8, t.raw_window};
   return HRRM_OK;
 }
 

@@ -54,6 +54,8 @@ void clear_error();
 TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h, int64_t d);
 int validate(const void* src, const void* dst, int dtype, int64_t w, int64_t h, int64_t d,
              int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r, int dims);
+int load_tuning(Context* c, const char* path);
+int save_tuning(const Context* c, const char* path);
 int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t stream,
                 bool use_graph);
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,

@@ -14,6 +14,7 @@ constexpr int kHash = 128;           // slot hash-table entries (power of two)
 constexpr int kMaxSlots = 64;        // tier slots per workgroup, slot 0 included
 constexpr int kMaxMiss = kBlock;     // misses collected per round
 constexpr int kLdsLimit = 160 * 1024;
+constexpr int kRawWindow = 81;       // (2r+1)^D up to this: missing subtrees counted raw
 
 // Adaptive topology node.  Internal nodes are numbered 0..2^d-2 (root 0).
 // A child >= 0 is an internal node; a child < 0 is the leaf holding grey value
@@ -38,6 +39,8 @@ struct MedianArgs {
   int32_t nslots;     // tier slots incl. slot 0 (tiered storage)
   int32_t min_group;  // smallest lane group counted cooperatively
   int32_t max_groups; // cooperative groups per level before falling back to direct sums
+  int32_t raw_window; // windows of at most this many values count a missing subtree raw
+  int32_t pad0;
   const TopoNode* topo;  // adaptive topology (device), else null
 };
 
@@ -58,6 +61,7 @@ struct TileConfig {
   int32_t max_groups;
   int32_t lds_budget; // bytes of LDS one workgroup may use
   int32_t tiered_u8;  // 1 = tiered storage for u8 as well
+  int32_t raw_window; // windows of at most this many values count deeper tiers raw
 };
 
 // Launch the fused median kernel.  dims = 2 or 3.  Returns hipSuccess or the

@@ -253,6 +253,43 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
   }
 }
 
+// Per-lane counts of a tier subtree straight from the raw window values (for
+// small windows this is cheaper than building the subtree's column vectors).
+template <typename T, bool ADAPT, bool D3>
+__device__ __forceinline__ void raw_counts(uint32_t (&W)[8], const T* __restrict__ src,
+                                           const MedianArgs& a, const TierState* ts,
+                                           const TopoNode* topo, int64_t x, int64_t y, int64_t z,
+                                           int node, int rlo, int rhi, int rdep) {
+  const int r = a.r, zr = D3 ? r : 0, bits = a.bits, stop = a.stop;
+  const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) W[i] = 0;
+  for (int dz = -zr; dz <= zr; ++dz) {
+    const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+    for (int dy = -r; dy <= r; ++dy) {
+      const T* rowp = src + zz * a.sss + clampi(y + dy, a.h - 1) * a.srs;
+      for (int dx = -r; dx <= r; ++dx) {
+        const int v = rowp[clampi(x + dx, a.w - 1)];
+        if (v >= rlo && v <= rhi) {
+          uint4 m;
+          if constexpr (ADAPT)
+            m = amask(topo, node, rdep, stop, v);
+          else
+            m = and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim);
+          W[0] += m.x & 0x00ff00ffu;
+          W[1] += (m.x >> 8) & 0x00ff00ffu;
+          W[2] += m.y & 0x00ff00ffu;
+          W[3] += (m.y >> 8) & 0x00ff00ffu;
+          W[4] += m.z & 0x00ff00ffu;
+          W[5] += (m.z >> 8) & 0x00ff00ffu;
+          W[6] += m.w & 0x00ff00ffu;
+          W[7] += (m.w >> 8) & 0x00ff00ffu;
+        }
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -398,6 +435,11 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   const int64_t x = x0 + lx;
   const uint32_t K = (uint32_t)a.rank;
   const int maxcol = D3 ? span * span : span;  // largest column count
+  // windows of at most kRawWindow values count a subtree no slot holds from the
+  // raw values; windows of at most a.raw_window values never hold deeper tiers
+  // in slots at all (every deeper tier is counted raw: no misses, no rebuilds)
+  const bool raw_fallback = maxcol * span <= kRawWindow;
+  const bool raw_only = maxcol * span <= a.raw_window;
   const int batch = 255 / maxcol > 0 ? 255 / maxcol : 1;
   const int maxrounds = ADAPT ? (3 * bits) / kTierLevels + 1 : (stop + kTierLevels - 1) / kTierLevels;
   int gr = 0;
@@ -444,7 +486,12 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           direct_counts(W, slots, cp16, slot, lx, span, batch);
         }
       }
-      // Pixels whose subtree no slot holds: one scratch build per subtree.
+      // Pixels whose subtree no slot holds: small windows count their raw
+      // values; otherwise the wave builds each such subtree once in scratch.
+      if (raw_fallback) {
+        if (act && slot < 0) raw_counts<T, ADAPT, D3>(W, src, a, ts, topo, x, y, z, node, lo, hi,
+                                                      depth);
+      } else
       for (uint64_t fb = ballot(act && slot < 0); fb;) {
         const int leader = __builtin_ctzll(fb);
         const int klo = readlane(lo, leader), khi = readlane(hi, leader);
@@ -501,6 +548,11 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
       // Tier transition: pixels entering a deeper subtree look up its slot;
       // subtrees no slot holds are queued as misses for thread 0.
       const bool exited = !done;
+      if (raw_only) {  // deeper tiers are all counted raw: no shared state, no barrier
+        if (exited) slot = -1;
+        if (ballot(exited) == 0) break;
+        continue;
+      }
       const int key = exited ? (ADAPT ? node : ukey(depth, lo >> (bits - depth))) : 0;
       const int b = gr % 3;
       if (tid == 0) ts->miss_n[(gr + 1) % 3] = 0;
@@ -663,13 +715,16 @@ __global__ __launch_bounds__(kBlock) void k_median_batched(const BatchImage* __r
       else
         lo = mid + 1;
     }
-    const BatchImage& bi = imgs[lo];
-    const int64_t local = t - (bi.tile_end - (int64_t)bi.args.strips * bi.args.segs);
-    const int strip = (int)(local % bi.args.strips), seg = (int)(local / bi.args.strips);
-    if (bi.bytes == 1)
-      tile_body<uint8_t, false, false>(bi.args, lds, strip, seg, 0);
+    // the image's arguments into registers once (the tile body reads them in
+    // its inner loops)
+    const MedianArgs args = imgs[lo].args;
+    const int bytes = imgs[lo].bytes;
+    const int64_t local = t - (imgs[lo].tile_end - (int64_t)args.strips * args.segs);
+    const int strip = (int)(local % args.strips), seg = (int)(local / args.strips);
+    if (bytes == 1)
+      tile_body<uint8_t, false, false>(args, lds, strip, seg, 0);
     else
-      tile_body<uint16_t, false, false>(bi.args, lds, strip, seg, 0);
+      tile_body<uint16_t, false, false>(args, lds, strip, seg, 0);
     __syncthreads();  // LDS is reused by the next tile
   }
 }

@@ -120,6 +120,7 @@ struct Server {
   std::deque<uint64_t> queue;
   std::vector<uint64_t> staged;
   std::vector<Running> running;
+  std::deque<uint64_t> finished;  // done tickets not yet reported by drain()
   int inflight = 0;
   uint64_t next_ticket = 1;
   std::atomic<bool> stop{false};
@@ -147,6 +148,7 @@ bool Server::step() {
         it->second.st = St::Done;
         it->second.t_done = t;
         arena.release(it->second.off_in, it->second.in_bytes);
+        finished.push_back(tk);
       }
       (void)hipEventDestroy(running[i].ev);
       running.erase(running.begin() + i);
@@ -174,9 +176,15 @@ bool Server::step() {
     r.off_in = oi;
     r.off_out = oo;
     const size_t b = bpp(r.req.dtype);
-    hipError_t e = hipMemcpy2DAsync(base + oi, (size_t)r.req.width * b, r.req.src,
-                                    (size_t)r.req.src_row_stride * b, (size_t)r.req.width * b,
-                                    (size_t)r.req.height, hipMemcpyHostToDevice, copy);
+    // packed rows: one linear copy (full link speed from pinned memory); strided
+    // rows: a 2-D copy, which the runtime performs far more slowly
+    hipError_t e = r.req.src_row_stride == r.req.width
+                       ? hipMemcpyAsync(base + oi, r.req.src, r.in_bytes, hipMemcpyHostToDevice,
+                                        copy)
+                       : hipMemcpy2DAsync(base + oi, (size_t)r.req.width * b, r.req.src,
+                                          (size_t)r.req.src_row_stride * b,
+                                          (size_t)r.req.width * b, (size_t)r.req.height,
+                                          hipMemcpyHostToDevice, copy);
     r.st = St::Admitted;
     r.t_admit = now();
     ++inflight;
@@ -185,6 +193,7 @@ bool Server::step() {
       r.st = St::Done;
       r.t_done = r.t_admit;
       arena.release(oi, r.in_bytes);
+      finished.push_back(*qi);
     } else {
       staged.push_back(*qi);
     }
@@ -246,6 +255,7 @@ bool Server::step() {
         r.st = St::Done;
         r.t_done = t;
         arena.release(r.off_in, r.in_bytes);
+        finished.push_back(tk);
       }
       if (ev) (void)hipEventDestroy(ev);
     } else {
@@ -370,6 +380,32 @@ int hrrm_server_poll(hrrm_server srv, uint64_t ticket, hrrm_result* res) {
   res->t_admit = r.t_admit;
   res->t_done = r.t_done;
   return HRRM_OK;
+}
+
+int hrrm_server_drain(hrrm_server srv, uint64_t* tickets, hrrm_result* results, int32_t max) {
+  Server* s = reinterpret_cast<Server*>(srv);
+  if (!s || !tickets || !results || max < 0) return fail(HRRM_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  int n = 0;
+  while (n < max && !s->finished.empty()) {
+    const uint64_t t = s->finished.front();
+    s->finished.pop_front();
+    auto it = s->items.find(t);
+    if (it == s->items.end()) continue;  // already released after a poll
+    const Item& r = it->second;
+    tickets[n] = t;
+    hrrm_result& res = results[n];
+    res.d_dst = s->base + r.off_out;
+    res.width = r.req.width;
+    res.height = r.req.height;
+    res.dtype = r.req.dtype;
+    res.status = r.status;
+    res.t_submit = r.t_submit;
+    res.t_admit = r.t_admit;
+    res.t_done = r.t_done;
+    ++n;
+  }
+  return n;
 }
 
 int hrrm_server_release(hrrm_server srv, uint64_t ticket) {

@@ -112,9 +112,10 @@ class Request:
     dtype: str  # "u8" or "u16"
     radius: int
     seed: int
-    pool_index: int = 0  # which pre-generated u16 pool image a crop comes from
-    offset_x: int = 0
+    pool_index: int = 0  # which pre-drawn pool image the pixels come from
+    offset_x: int = 0    # crop origin in the pool image
     offset_y: int = 0
+    offset_flat: int = 0  # start of a packed w*h run of the flattened pool image
 
 
 SERVING_RADII = (1, 2, 3, 7, 15, 31)
@@ -124,8 +125,9 @@ def serving_trace(duration_s: float = 5.0, rate_hz: float = 2000.0, seed: int = 
                   min_side: int = 256, max_side: int = 4096, pool_images: int = 4,
                   pool_side: int = 4096, max_requests: Optional[int] = None) -> List[Request]:
     """Poisson arrivals; W, H ~ U{min_side..max_side}; half u8, half u16;
-    radius uniform over SERVING_RADII.  u16 requests are crops of pre-drawn
-    X-ray-like pool images at seeded offsets (host memory stays bounded)."""
+    radius uniform over SERVING_RADII.  Requests are crops, at seeded offsets,
+    of pre-drawn pool images (uniform u8 pool images for u8 requests, X-ray-like
+    u16 pool images for u16 requests), so host memory stays bounded."""
     g = rng(seed)
     out: List[Request] = []
     t = 0.0
@@ -139,25 +141,38 @@ def serving_trace(duration_s: float = 5.0, rate_hz: float = 2000.0, seed: int = 
         is16 = bool(g.integers(0, 2))
         rad = int(SERVING_RADII[int(g.integers(0, len(SERVING_RADII)))])
         req = Request(t, w, h, "u16" if is16 else "u8", rad, seed=1000 + i)
-        if is16:
-            req.pool_index = int(g.integers(0, pool_images))
-            req.offset_x = int(g.integers(0, pool_side - w + 1))
-            req.offset_y = int(g.integers(0, pool_side - h + 1))
+        req.pool_index = int(g.integers(0, pool_images))
+        req.offset_x = int(g.integers(0, pool_side - w + 1))
+        req.offset_y = int(g.integers(0, pool_side - h + 1))
+        req.offset_flat = int(g.integers(0, pool_side * pool_side - w * h + 1))
         out.append(req)
         i += 1
     return out
 
 
-def serving_pool(pool_images: int = 4, pool_side: int = 4096, seed: int = 4) -> Iterator[np.ndarray]:
+def serving_pool(pool_images: int = 4, pool_side: int = 4096, seed: int = 4,
+                 dtype: str = "u16") -> Iterator[np.ndarray]:
     for k in range(pool_images):
-        yield xray_u16(pool_side, pool_side, seed=10_000 + seed * 100 + k)
+        if dtype == "u16":
+            yield xray_u16(pool_side, pool_side, seed=10_000 + seed * 100 + k)
+        else:
+            yield uniform_u8(pool_side, pool_side, seed=20_000 + seed * 100 + k)
 
 
-def request_pixels(req: Request, pool: Optional[List[np.ndarray]] = None) -> np.ndarray:
-    if req.dtype == "u8":
-        return uniform_u8(req.height, req.width, seed=req.seed)
+def request_pixels(req: Request, pool: Optional[List[np.ndarray]] = None,
+                   packed: bool = False) -> np.ndarray:
+    """The request's pixels: a crop of its pool image, or with packed=True the
+    w*h consecutive pool pixels from offset_flat laid out as rows of width w
+    (same value distribution, contiguous in host memory); without a pool, a
+    fresh image of the same kind."""
     if pool is None:
+        if req.dtype == "u8":
+            return uniform_u8(req.height, req.width, seed=req.seed)
         return xray_u16(req.height, req.width, seed=req.seed)
     src = pool[req.pool_index % len(pool)]
+    if packed:
+        flat = src.reshape(-1)
+        return flat[req.offset_flat:req.offset_flat + req.width * req.height].reshape(
+            req.height, req.width)
     return np.ascontiguousarray(
         src[req.offset_y:req.offset_y + req.height, req.offset_x:req.offset_x + req.width])
