@@ -24,7 +24,8 @@ namespace hrrm {
 
 namespace {
 constexpr int kBatchCap = 4096;           // images per batch
-constexpr size_t kBatchLds = 80 * 1024;   // dynamic LDS per workgroup: two workgroups per CU
+// dynamic LDS per workgroup: with the kernel's few static bytes two workgroups fit a CU
+constexpr size_t kBatchLds = 80 * 1024 - 256;
 constexpr int kBatchMaxR = 127;
 }  // namespace
 
@@ -121,6 +122,20 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
   if (descs.empty()) return HRRM_OK;
+  // longest work first: expensive images (16-bit, larger windows) at the front
+  // of every chunk's range shortens the tail of the launch
+  std::stable_sort(descs.begin(), descs.end(), [](const BatchImage& x, const BatchImage& y) {
+    const double cx = (double)x.args.w * x.args.h * (x.bytes == 2 ? 3.0 : 1.0) *
+                      (1.0 + x.args.r / 16.0);
+    const double cy = (double)y.args.w * y.args.h * (y.bytes == 2 ? 3.0 : 1.0) *
+                      (1.0 + y.args.r / 16.0);
+    return cx > cy;
+  });
+  tiles = 0;
+  for (auto& d : descs) {
+    tiles += (int64_t)d.args.strips * d.args.segs;
+    d.tile_end = tiles;
+  }
   BatchStream* bs = ctx->batch_for(stream);
   if (!bs) return fail(HRRM_ENOMEM, "batch descriptor buffers");
   // device buffer: work counter at byte 0, image count at byte 64, descriptors

@@ -693,7 +693,11 @@ __global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
 // Persistent batched launch: every workgroup repeatedly takes the next tile
 // index from a device counter and runs the tile body for whichever image the
 // tile belongs to (plain 2-D median, 8- or 16-bit).  Tiles of one image are
-// contiguous in the index space, images in descriptor order.
+// contiguous in the index space, images in descriptor order.  The index space
+// is cut into 8 contiguous chunks with a counter each; workgroups start on the
+// chunk of their XCD (workgroups are dealt to XCDs round-robin) so that tiles
+// sharing halo rows stay in one XCD's L2, and move on to the other chunks when
+// theirs is exhausted.
 __global__ __launch_bounds__(kBlock) void k_median_batched(const BatchImage* __restrict__ imgs,
                                                            const int32_t* __restrict__ hdr,
                                                            uint32_t* __restrict__ counter) {
@@ -701,36 +705,44 @@ __global__ __launch_bounds__(kBlock) void k_median_batched(const BatchImage* __r
   __shared__ int s_tile;
   const int n = hdr[0];
   const int64_t total = n > 0 ? imgs[n - 1].tile_end : 0;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int64_t t = s_tile;
-    __syncthreads();  // every thread has read s_tile before thread 0 overwrites it
-    if (t >= total) break;
-    int lo = 0, hi = n - 1;  // first image whose tile range ends after t
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (imgs[mid].tile_end > t)
-        hi = mid;
+  const int64_t per = (total + 7) / 8;
+  const int home = blockIdx.x & 7;
+  for (int c = 0; c < 8; ++c) {
+    const int chunk = (home + c) & 7;
+    const int64_t c0 = chunk * per, c1 = c0 + per < total ? c0 + per : total;
+    for (;;) {
+      if (threadIdx.x == 0) s_tile = (int)atomicAdd(&counter[chunk], 1u);
+      __syncthreads();
+      // uniform by construction; readfirstlane lets the compiler keep the tile
+      // index, the image search and the image's arguments in scalar registers
+      const int64_t t = c0 + __builtin_amdgcn_readfirstlane(s_tile);
+      __syncthreads();  // every thread has read s_tile before thread 0 overwrites it
+      if (t >= c1) break;
+      int lo = 0, hi = n - 1;  // first image whose tile range ends after t
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (imgs[mid].tile_end > t)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      // the image's arguments into registers once (the tile body reads them in
+      // its inner loops)
+      const MedianArgs args = imgs[lo].args;
+      const int bytes = imgs[lo].bytes;
+      const int64_t local = t - (imgs[lo].tile_end - (int64_t)args.strips * args.segs);
+      const int strip = (int)(local % args.strips), seg = (int)(local / args.strips);
+      if (bytes == 1)
+        tile_body<uint8_t, false, false>(args, lds, strip, seg, 0);
       else
-        lo = mid + 1;
+        tile_body<uint16_t, false, false>(args, lds, strip, seg, 0);
+      __syncthreads();  // LDS is reused by the next tile
     }
-    // the image's arguments into registers once (the tile body reads them in
-    // its inner loops)
-    const MedianArgs args = imgs[lo].args;
-    const int bytes = imgs[lo].bytes;
-    const int64_t local = t - (imgs[lo].tile_end - (int64_t)args.strips * args.segs);
-    const int strip = (int)(local % args.strips), seg = (int)(local / args.strips);
-    if (bytes == 1)
-      tile_body<uint8_t, false, false>(args, lds, strip, seg, 0);
-    else
-      tile_body<uint16_t, false, false>(args, lds, strip, seg, 0);
-    __syncthreads();  // LDS is reused by the next tile
   }
 }
 
 __global__ void k_zero_counter(uint32_t* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+  if (threadIdx.x < 8 && blockIdx.x == 0) counter[threadIdx.x] = 0;
 }
 
 template <typename T, bool ADAPT, bool D3>
