@@ -166,7 +166,8 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
 
   if (tiered) {
     const size_t meta = median_lds_bytes(bytes, adaptive, true, a.ncols, a.cp, 0);
-    const size_t slot_bytes = (size_t)a.cp * 16;  // one 16-byte tier vector per column
+    // one 16-byte tier vector per column, plus (adaptive) the subtree's topology
+    const size_t slot_bytes = (size_t)a.cp * 16 + (adaptive ? tiered_topo_bytes(1) : 0);
     const size_t budget = (size_t)std::min(std::max(t.lds_budget, 16 * 1024), kLdsLimit);
     int fit = budget > meta ? (int)((budget - meta) / slot_bytes) : 0;
     int ns = t.nslots > 0 ? t.nslots : fit;

@@ -72,8 +72,10 @@ hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive
 // LDS bytes a launch with these parameters needs.
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);
 
-// Tiered-kernel LDS bytes besides the slots, for radius r.
+// Tiered-kernel LDS bytes besides the slots, for radius r; adaptive trees add
+// tiered_topo_bytes(nslots) for the held subtrees' topology.
 size_t tiered_meta_bytes(int r);
+size_t tiered_topo_bytes(int nslots);
 
 // Persistent batched launch (zeroes *d_counter first, then runs `grid`
 // workgroups over all tiles of the images in d_imgs; d_hdr[0] = image count).

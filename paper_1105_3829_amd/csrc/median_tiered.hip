@@ -134,6 +134,47 @@ __device__ __forceinline__ uint4 amask(const TopoNode* topo, int node, int dep, 
   return make_uint4(m[0], m[1], m[2], m[3]);
 }
 
+// Adaptive trees: LDS copy of a held tier subtree's topology, 16 entries per
+// slot (entry p-1 = the node at heap position p of the subtree, split < 0 =
+// no node there).  The children of positions 8..15 are the roots of the next
+// tier.  Filled from the global table when a slot is assigned.
+__device__ __forceinline__ void fill_subtree(TopoNode* st, const TopoNode* topo, int root) {
+  st[0] = topo[root];
+  for (int p = 1; p <= 7; ++p) {
+    const TopoNode e = st[p - 1];
+    const TopoNode none = {-1, -1, -1, 0};
+    st[2 * p - 1] = (e.split >= 0 && e.left >= 0) ? topo[e.left] : none;
+    st[2 * p] = (e.split >= 0 && e.right >= 0) ? topo[e.right] : none;
+  }
+  const TopoNode none = {-1, -1, -1, 0};
+  st[15] = none;
+}
+
+// Insertion mask of value v in a held adaptive subtree (its LDS topology);
+// *next receives the node the value reaches below the subtree (< 0: a leaf).
+__device__ __forceinline__ uint4 smask(const TopoNode* st, int dep, int stop, int v, int* next) {
+  uint32_t m[4] = {0u, 0u, 0u, 0u};
+  int p = 1, nd = 0;
+#pragma unroll
+  for (int k = 0; k < kTierLevels; ++k) {
+    if (dep + k >= stop) {
+      nd = -1;
+      break;
+    }
+    const TopoNode t = st[p - 1];
+    const bool left = v < t.split;
+    if (left) {
+      const int b = p - 1;
+      m[b >> 2] |= 1u << ((b & 3) * 8);
+    }
+    nd = left ? t.left : t.right;
+    if (nd < 0) break;
+    p = 2 * p + (left ? 0 : 1);
+  }
+  *next = nd;
+  return make_uint4(m[0], m[1], m[2], m[3]);
+}
+
 // Count of node q (0..14) from the packed window counts: word 2i holds nodes
 // 4i and 4i+2, word 2i+1 nodes 4i+1 and 4i+3 (16-bit fields).
 __device__ __forceinline__ uint32_t wsel(const uint32_t (&W)[8], int q) {
@@ -300,7 +341,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // held subtrees below a replaced slot (their updates walk down from the top and
 // stop at the first subtree no slot holds).
 template <bool ADAPT>
-__device__ void assign_slots(TierState* ts, int nmiss, int stamp, int nslots) {
+__device__ void assign_slots(TierState* ts, int nmiss, int stamp, int nslots, TopoNode* stopo,
+                             const TopoNode* topo) {
   int nreb = 0;
   for (int i = 0; i < nmiss; ++i) {
     const int key = ts->miss[i][0];
@@ -336,10 +378,12 @@ __device__ void assign_slots(TierState* ts, int nmiss, int stamp, int nslots) {
     ts->hi[victim] = ts->miss[i][2];
     ts->dep[victim] = ts->miss[i][3];
     ts->stamp[victim] = stamp;
-    if constexpr (ADAPT)
+    if constexpr (ADAPT) {
       ht_insert(ts->ht, key, victim);
-    else
+      fill_subtree(stopo + victim * 16, topo, key);
+    } else {
       ts->smap[key] = (uint8_t)victim;
+    }
     ts->reb[nreb][0] = victim;
     ts->reb[nreb][1] = key;
     ts->reb[nreb][2] = ts->miss[i][1];
@@ -373,6 +417,9 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   // per-wave scratch of (64 + 2r + 1) column vectors for subtrees no slot holds
   uint8_t* scr = lds + align16((size_t)a.nslots * cp16) + align16(sizeof(TierState)) +
                  (size_t)wv * (64 + span) * 16;
+  // adaptive: topology of each held subtree (16 entries per slot) after the scratch
+  TopoNode* stopo = (TopoNode*)(lds + align16((size_t)a.nslots * cp16) +
+                                align16(sizeof(TierState)) + (size_t)kWaves * (64 + span) * 16);
   const int root = ADAPT ? topo[(1 << bits) - 1].split : 1;
   const int maxv = (1 << bits) - 1;
   const int ntiers = (bits + kTierLevels - 1) / kTierLevels;
@@ -403,15 +450,17 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
     ts->key[0] = root;  // slot 0 holds tier 1 and is never replaced
     ts->stamp[0] = 0x7fffffff;
     ts->hi[0] = maxv;
+    if constexpr (ADAPT) fill_subtree(stopo, topo, root);
   }
   __syncthreads();
 
   // Tier-1 insertion mask of value v.
   const uint4 lim1 = level_mask(stop < kTierLevels ? stop : kTierLevels);
   auto mask1 = [&](int v) -> uint4 {
-    if constexpr (ADAPT)
-      return amask(topo, root, 0, stop, v);
-    else
+    if constexpr (ADAPT) {
+      int nx;
+      return smask(stopo, 0, stop, v, &nx);
+    } else
       return and4(ts->lut[(v >> (bits - kTierLevels)) & 15], lim1);
   };
 
@@ -513,7 +562,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
             int split, lch = 0, rch = 0;
             bool lleaf, rleaf;
             if constexpr (ADAPT) {
-              const TopoNode t = topo[node];
+              const TopoNode t = slot >= 0 ? stopo[slot * 16 + p - 1] : topo[node];
               split = t.split;
               lch = t.left;
               rch = t.right;
@@ -588,7 +637,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
       ++gr;
       if (!any) break;
       if (nmiss > 0) {
-        if (tid == 0) assign_slots<ADAPT>(ts, nmiss, (int)y, a.nslots);
+        if (tid == 0) assign_slots<ADAPT>(ts, nmiss, (int)y, a.nslots, stopo, topo);
         __syncthreads();
         const int nreb = ts->reb_n;
         if (nreb > 0) {
@@ -608,10 +657,12 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                 for (int j = -r; j <= r; ++j) {
                   const int v = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
                   if (v >= rlo && v <= rhi) {
-                    if constexpr (ADAPT)
-                      c = add4(c, amask(topo, rkey, rdep, stop, v));
-                    else
+                    if constexpr (ADAPT) {
+                      int nx;
+                      c = add4(c, smask(stopo + rs * 16, rdep, stop, v, &nx));
+                    } else {
                       c = add4(c, and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim));
+                    }
                   }
                 }
               }
@@ -641,7 +692,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
               const int v = D3 ? (int)src[zz * a.sss + yy * a.srs + cx]
                                : (pass == 0 ? pre_o[lc >= kBlock] : pre_i[lc >= kBlock]);
               if constexpr (ADAPT) {
-                // walk down the tiers while their subtrees are held
+                // walk down the tiers while their subtrees are held (each held
+                // subtree's topology is in LDS)
                 int nd = root, s = 0, dep = 0;
                 for (int t = 0; t <= (3 * bits) / kTierLevels && nd >= 0 && dep < stop; ++t) {
                   if (t > 0) {
@@ -649,12 +701,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                     if (s < 0) break;
                   }
                   uint4& cv = vec(slots, cp16, s, lc);
-                  const uint4 m = amask(topo, nd, dep, stop, v);
+                  const uint4 m = smask(stopo + s * 16, dep, stop, v, &nd);
                   cv = pass == 0 ? sub4(cv, m) : add4(cv, m);
-                  for (int k = 0; k < kTierLevels && nd >= 0; ++k) {
-                    const TopoNode tn = topo[nd];
-                    nd = v < tn.split ? tn.left : tn.right;
-                  }
                   dep += kTierLevels;
                 }
               } else {
@@ -776,6 +824,8 @@ hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32
 size_t tiered_meta_bytes(int r) {
   return align16_host(sizeof(TierState)) + (size_t)kWaves * (64 + 2 * r + 1) * 16;
 }
+
+size_t tiered_topo_bytes(int nslots) { return (size_t)nslots * 16 * sizeof(TopoNode); }
 
 hipError_t launch_median_tiered(const MedianArgs& a, int bytes, int dims, bool adaptive,
                                 size_t lds, hipStream_t stream) {

@@ -61,29 +61,42 @@ __global__ void k_zero(uint32_t* p, size_t n) {
     p[i] = 0;
 }
 
+// Workgroup-private histograms: 16-bit bins in LDS (2^bits x 2 bytes, 128 KB
+// for 16-bit data), one workgroup per block of at most 65535 values so no bin
+// overflows, updated with dword atomics on the bin's half (no carry: a bin
+// never exceeds 65535), then the non-zero bins are added to the global
+// histogram.  This keeps the device-wide atomics off the hot bins of compact
+// distributions.
+__device__ __forceinline__ void lds_bin_add(uint32_t* lh, uint32_t v) {
+  atomicAdd(&lh[v >> 1], 1u << ((v & 1) * 16));
+}
+
+__device__ __forceinline__ void lds_hist_flush(const uint32_t* lh, uint32_t* hist, int nbins) {
+  for (int i = threadIdx.x; i < nbins / 2; i += kTB) {
+    const uint32_t p = lh[i];
+    if (p & 0xffffu) atomicAdd(&hist[2 * i], p & 0xffffu);
+    if (p >> 16) atomicAdd(&hist[2 * i + 1], p >> 16);
+  }
+}
+
+constexpr int64_t kHistBlock = 65535;  // values per workgroup (16-bit bins)
+
 template <typename T>
 __global__ __launch_bounds__(kTB) void k_hist(MedianArgs a, uint32_t* hist) {
-  __shared__ uint32_t lh[256];
+  extern __shared__ uint32_t lh[];
+  const int nbins = 1 << (8 * sizeof(T));
   const T* src = (const T*)a.src;
-  const bool small = sizeof(T) == 1;
-  if (small) {
-    for (int i = threadIdx.x; i < 256; i += kTB) lh[i] = 0;
-    __syncthreads();
-  }
+  for (int i = threadIdx.x; i < nbins / 2; i += kTB) lh[i] = 0;
+  __syncthreads();
   const int64_t n = a.w * a.h * a.d;
-  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+  const int64_t b0 = (int64_t)blockIdx.x * kHistBlock;
+  const int64_t b1 = b0 + kHistBlock < n ? b0 + kHistBlock : n;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += kTB) {
     const int64_t x = i % a.w, t = i / a.w, y = t % a.h, z = t / a.h;
-    const uint32_t v = src[z * a.sss + y * a.srs + x];
-    if (small)
-      atomicAdd(&lh[v], 1u);
-    else
-      atomicAdd(&hist[v], 1u);
+    lds_bin_add(lh, src[z * a.sss + y * a.srs + x]);
   }
-  if (small) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < 256; i += kTB)
-      if (lh[i]) atomicAdd(&hist[i], lh[i]);
-  }
+  __syncthreads();
+  lds_hist_flush(lh, hist, nbins);
 }
 
 __device__ __forceinline__ int64_t cl(int64_t v, int64_t hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
@@ -96,7 +109,12 @@ template <typename Tin, bool HIST>
 __global__ __launch_bounds__(kTB) void k_box(const Tin* in, int64_t s0, int64_t s1, int64_t s2,
                                              int axis, int64_t w, int64_t h, int64_t d, int r,
                                              int seg, uint32_t* out, uint32_t* hist,
-                                             uint32_t nwin) {
+                                             uint32_t nwin, int nbins) {
+  extern __shared__ uint32_t lh[];
+  if (HIST) {  // one workgroup histograms at most 256 * seg <= 65535 means
+    for (int i = threadIdx.x; i < nbins / 2; i += kTB) lh[i] = 0;
+    __syncthreads();
+  }
   const int64_t dims[3] = {w, h, d};
   const int64_t len = dims[axis];
   const int64_t oa = axis == 0 ? 1 : 0, ob = axis == 2 ? 1 : 2;  // the two other axes
@@ -122,10 +140,14 @@ __global__ __launch_bounds__(kTB) void k_box(const Tin* in, int64_t s0, int64_t 
         s += (uint32_t)in[ibase + cl(p + r, len - 1) * st] -
              (uint32_t)in[ibase + cl(p - r - 1, len - 1) * st];
       if (HIST)
-        atomicAdd(&hist[s / nwin], 1u);
+        lds_bin_add(lh, s / nwin);
       else
         out[obase + p * so] = s;
     }
+  }
+  if (HIST) {
+    __syncthreads();
+    lds_hist_flush(lh, hist, nbins);
   }
 }
 
@@ -228,40 +250,48 @@ hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* wsp, 
   // the two histograms are adjacent: clear both in one go
   hipLaunchKernelGGL(k_zero, dim3(64), dim3(kTB), 0, stream,
                      w.hist_src, (size_t)(((char*)w.hist_mean - (char*)w.hist_src) / 4 + nb));
-  const int hgrid = (int)std::min<int64_t>((pixels + kTB - 1) / kTB, 4096);
-  if (bytes == 1)
-    hipLaunchKernelGGL(k_hist<uint8_t>, dim3(hgrid), dim3(kTB), 0, stream, a, w.hist_src);
-  else
-    hipLaunchKernelGGL(k_hist<uint16_t>, dim3(hgrid), dim3(kTB), 0, stream, a, w.hist_src);
+  const int hgrid = (int)((pixels + kHistBlock - 1) / kHistBlock);
+  const size_t hlds = nb * 2;  // 16-bit bins
+  if (bytes == 1) {
+    hipLaunchKernelGGL(k_hist<uint8_t>, dim3(hgrid), dim3(kTB), hlds, stream, a, w.hist_src);
+  } else {
+    (void)hipFuncSetAttribute((const void*)k_hist<uint16_t>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)hlds);
+    (void)hipFuncSetAttribute((const void*)k_box<uint32_t, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)hlds);
+    hipLaunchKernelGGL(k_hist<uint16_t>, dim3(hgrid), dim3(kTB), hlds, stream, a, w.hist_src);
+  }
 
   // running box mean over the same window: separable clamp-to-edge sums
   const int seg = 64;
   const uint32_t nwin = (uint32_t)((dims == 3 ? (2 * a.r + 1) : 1) * (2 * a.r + 1) * (2 * a.r + 1));
+  // the histogramming pass runs one thread per (line, segment) with no grid
+  // stride, so each workgroup covers at most 256 * seg values
   auto grid_for = [&](int axis) {
     const int64_t len = axis == 0 ? a.w : (axis == 1 ? a.h : a.d);
     const int64_t lines = pixels / len;
     const int64_t total = lines * ((len + seg - 1) / seg);
-    return (int)std::min<int64_t>((total + kTB - 1) / kTB, 65535);
+    return (int)((total + kTB - 1) / kTB);
   };
   if (bytes == 1)
     hipLaunchKernelGGL((k_box<uint8_t, false>), dim3(grid_for(0)), dim3(kTB), 0, stream,
                        (const uint8_t*)a.src, (int64_t)1, a.srs, a.sss, 0, a.w, a.h, a.d, a.r,
-                       seg, w.box[0], nullptr, 1u);
+                       seg, w.box[0], nullptr, 1u, 0);
   else
     hipLaunchKernelGGL((k_box<uint16_t, false>), dim3(grid_for(0)), dim3(kTB), 0, stream,
                        (const uint16_t*)a.src, (int64_t)1, a.srs, a.sss, 0, a.w, a.h, a.d, a.r,
-                       seg, w.box[0], nullptr, 1u);
+                       seg, w.box[0], nullptr, 1u, 0);
   if (dims == 3) {
     hipLaunchKernelGGL((k_box<uint32_t, false>), dim3(grid_for(1)), dim3(kTB), 0, stream,
                        (const uint32_t*)w.box[0], (int64_t)1, a.w, a.w * a.h, 1, a.w, a.h, a.d,
-                       a.r, seg, w.box[1], nullptr, 1u);
-    hipLaunchKernelGGL((k_box<uint32_t, true>), dim3(grid_for(2)), dim3(kTB), 0, stream,
+                       a.r, seg, w.box[1], nullptr, 1u, 0);
+    hipLaunchKernelGGL((k_box<uint32_t, true>), dim3(grid_for(2)), dim3(kTB), hlds, stream,
                        (const uint32_t*)w.box[1], (int64_t)1, a.w, a.w * a.h, 2, a.w, a.h, a.d,
-                       a.r, seg, nullptr, w.hist_mean, nwin);
+                       a.r, seg, nullptr, w.hist_mean, nwin, (int)nb);
   } else {
-    hipLaunchKernelGGL((k_box<uint32_t, true>), dim3(grid_for(1)), dim3(kTB), 0, stream,
+    hipLaunchKernelGGL((k_box<uint32_t, true>), dim3(grid_for(1)), dim3(kTB), hlds, stream,
                        (const uint32_t*)w.box[0], (int64_t)1, a.w, a.w * a.h, 1, a.w, a.h, a.d,
-                       a.r, seg, nullptr, w.hist_mean, nwin);
+                       a.r, seg, nullptr, w.hist_mean, nwin, (int)nb);
   }
   hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, stream, w.hist_src, w.hist_mean, w.prefix,
                      (int)nb);
