@@ -54,6 +54,7 @@ struct TierState {
   int32_t flag[3][kWaves];
   int32_t reb_n;
   int32_t pad;
+  uint32_t vand, vor;            // AND / OR of every value the tile reads
   int32_t miss[kMissCap][4];     // key, lo, hi, depth of a subtree root nobody holds
   int32_t reb[kMaxSlots][4];     // slot, key, lo, depth of a slot to rebuild
 };
@@ -83,9 +84,18 @@ __device__ __forceinline__ void ht_insert(uint32_t* ht, int key, int slot) {
   }
 }
 
-// Uniform tree: table index of the tier subtree rooted at depth `dep` (4, 8,
-// 12) containing values with prefix `pre` = value >> (bits - dep).
-__device__ __forceinline__ int ukey(int dep, int pre) { return (((1 << dep) - 16) / 15) + pre; }
+// Uniform tree: table index of the tier subtree whose root lies `rel` (4, 8,
+// 12) levels below the tile's first tier, for values whose `rel` bits below
+// the tile's common prefix are `pre`.
+__device__ __forceinline__ int ukey(int rel, int pre) { return (((1 << rel) - 16) / 15) + pre; }
+
+// Uniform tree: the four value bits that choose the path through the tier
+// subtree rooted at depth `dep` (bits past the last level read as zero; the
+// level mask drops the levels they would select).
+__device__ __forceinline__ int nib(int v, int dep, int bits) {
+  const int s = bits - dep - kTierLevels;
+  return (s >= 0 ? v >> s : v << -s) & 15;
+}
 
 // Bytes of the levels of a tier subtree that are maintained: levels
 // 0..nlev-1 occupy bytes 0 .. 2^nlev - 2.
@@ -272,7 +282,8 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
                                               const TopoNode* topo, int64_t x0w, int64_t y,
                                               int64_t z, int lane, int span, int node, int rlo,
                                               int rhi, int rdep) {
-  const int r = a.r, zr = D3 ? r : 0, bits = a.bits, stop = a.stop;
+  constexpr int bits = 8 * sizeof(T);
+  const int r = a.r, zr = D3 ? r : 0, stop = a.stop;
   const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
   for (int c = lane; c <= 64 + span - 1; c += 64) {
     const int64_t cx = clampi(x0w - r - 1 + c, a.w - 1);
@@ -286,7 +297,7 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
           if constexpr (ADAPT)
             acc = add4(acc, amask(topo, node, rdep, stop, v));
           else
-            acc = add4(acc, and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim));
+            acc = add4(acc, and4(ts->lut[nib(v, rdep, bits)], lim));
         }
       }
     }
@@ -301,7 +312,8 @@ __device__ __forceinline__ void raw_counts(uint32_t (&W)[8], const T* __restrict
                                            const MedianArgs& a, const TierState* ts,
                                            const TopoNode* topo, int64_t x, int64_t y, int64_t z,
                                            int node, int rlo, int rhi, int rdep) {
-  const int r = a.r, zr = D3 ? r : 0, bits = a.bits, stop = a.stop;
+  constexpr int bits = 8 * sizeof(T);
+  const int r = a.r, zr = D3 ? r : 0, stop = a.stop;
   const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
 #pragma unroll
   for (int i = 0; i < 8; ++i) W[i] = 0;
@@ -316,7 +328,7 @@ __device__ __forceinline__ void raw_counts(uint32_t (&W)[8], const T* __restrict
           if constexpr (ADAPT)
             m = amask(topo, node, rdep, stop, v);
           else
-            m = and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim);
+            m = and4(ts->lut[nib(v, rdep, bits)], lim);
           W[0] += m.x & 0x00ff00ffu;
           W[1] += (m.x >> 8) & 0x00ff00ffu;
           W[2] += m.y & 0x00ff00ffu;
@@ -402,7 +414,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   const T* __restrict__ src = (const T*)a.src;
   T* __restrict__ dst = (T*)a.dst;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int r = a.r, ncols = a.ncols, bits = a.bits, stop = a.stop;
+  constexpr int bits = 8 * sizeof(T);  // the tree height of the uniform tree
+  const int r = a.r, ncols = a.ncols, stop = a.stop;
   const int span = 2 * r + 1;
   const int zr = D3 ? r : 0;
   const size_t cp16 = (size_t)a.cp * 16;  // bytes of one slot (cp >= ncols columns)
@@ -447,6 +460,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   if (tid < 3 * kWaves) ts->flag[tid / kWaves][tid % kWaves] = 0;
   if (tid == 0) {
     ts->reb_n = 0;
+    ts->vand = 0xffffffffu;
+    ts->vor = 0u;
     ts->key[0] = root;  // slot 0 holds tier 1 and is never replaced
     ts->stamp[0] = 0x7fffffff;
     ts->hi[0] = maxv;
@@ -454,14 +469,43 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   }
   __syncthreads();
 
-  // Tier-1 insertion mask of value v.
-  const uint4 lim1 = level_mask(stop < kTierLevels ? stop : kTierLevels);
+  // Uniform 2-D trees of 16-bit data: the top `pl` levels of every window's
+  // descent are fixed when all values the tile reads share their top `pl`
+  // bits (12-bit data in 16-bit pixels: the top four levels always go left).
+  // The tile's first tier then starts at depth pl with the common prefix `pfx`
+  // as its interval's lower bound; the output is the same.
+  int pl = 0, pfx = 0;
+  if constexpr (!ADAPT && !D3 && sizeof(T) == 2) {
+    const int64_t r0 = yb - r > 0 ? yb - r : 0;
+    const int64_t r1 = ye - 1 + r < a.h - 1 ? ye - 1 + r : a.h - 1;
+    uint32_t va = 0xffffffffu, vo = 0u;
+    for (int lc = tid; lc < ncols; lc += kBlock) {
+      const T* p = src + z * a.sss + clampi(x0 - r - 1 + lc, a.w - 1);
+#pragma unroll 4
+      for (int64_t yy = r0; yy <= r1; ++yy) {
+        const uint32_t v = p[yy * a.srs];
+        va &= v;
+        vo |= v;
+      }
+    }
+    atomicAnd(&ts->vand, va);
+    atomicOr(&ts->vor, vo);
+    __syncthreads();
+    const uint32_t diff = __builtin_amdgcn_readfirstlane(ts->vand ^ ts->vor);
+    pl = diff == 0u ? bits : __builtin_clz(diff) - (32 - bits);
+    if (pl > stop) pl = stop;
+    pfx = pl >= bits ? (int)__builtin_amdgcn_readfirstlane(ts->vand)
+                     : (int)(__builtin_amdgcn_readfirstlane(ts->vand) & ~((1u << (bits - pl)) - 1u));
+  }
+
+  // First-tier insertion mask of value v.
+  const uint4 lim1 = level_mask(stop - pl < kTierLevels ? stop - pl : kTierLevels);
   auto mask1 = [&](int v) -> uint4 {
     if constexpr (ADAPT) {
       int nx;
       return smask(stopo, 0, stop, v, &nx);
     } else
-      return and4(ts->lut[(v >> (bits - kTierLevels)) & 15], lim1);
+      return and4(ts->lut[nib(v, pl, bits)], lim1);
   };
 
   // ---- column trees (tier 1) of the segment's first window
@@ -509,10 +553,10 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         }
       }
     }
-    int node = root, lo = 0, hi = maxv, depth = 0;
+    int node = root, lo = pfx, hi = pfx + (int)((1u << (bits - pl)) - 1u), depth = pl;
     uint32_t acc = 0;
-    bool done = (x >= a.w) || (stop == 0);
-    int res = 0;
+    bool done = (x >= a.w) || (pl >= stop);
+    int res = pfx;
     int slot = 0;
 
     for (int round = 0; round <= maxrounds; ++round) {
@@ -602,7 +646,10 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         if (ballot(exited) == 0) break;
         continue;
       }
-      const int key = exited ? (ADAPT ? node : ukey(depth, lo >> (bits - depth))) : 0;
+      const int key = exited ? (ADAPT ? node
+                                      : ukey(depth - pl, (lo >> (bits - depth)) &
+                                                             ((1 << (depth - pl)) - 1)))
+                              : 0;
       const int b = gr % 3;
       if (tid == 0) ts->miss_n[(gr + 1) % 3] = 0;
       const uint64_t ex = ballot(exited);
@@ -661,7 +708,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                       int nx;
                       c = add4(c, smask(stopo + rs * 16, rdep, stop, v, &nx));
                     } else {
-                      c = add4(c, and4(ts->lut[(v >> (bits - rdep - kTierLevels)) & 15], lim));
+                      c = add4(c, and4(ts->lut[nib(v, rdep, bits)], lim));
                     }
                   }
                 }
@@ -707,14 +754,14 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                 }
               } else {
                 for (int t = 0; t < ntiers; ++t) {
-                  const int dep = t * kTierLevels;
+                  const int rel = t * kTierLevels, dep = pl + rel;
                   if (dep >= stop) break;
                   int s = 0;
                   if (t > 0) {
-                    s = ts->smap[ukey(dep, v >> (bits - dep))];
+                    s = ts->smap[ukey(rel, (v >> (bits - dep)) & ((1 << rel) - 1))];
                     if (s == (int)kNone) continue;
                   }
-                  const uint4 m = and4(ts->lut[(v >> (bits - dep - kTierLevels)) & 15],
+                  const uint4 m = and4(ts->lut[nib(v, dep, bits)],
                                        level_mask(stop - dep < kTierLevels ? stop - dep
                                                                            : kTierLevels));
                   uint4& cv = vec(slots, cp16, s, lc);
