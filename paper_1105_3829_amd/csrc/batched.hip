@@ -84,7 +84,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     if (im.r > kBatchMaxR) return fail(HRRM_EUNSUPPORTED, "image %d: radius %d", i, im.r);
     if (im.width == 0 || im.height == 0) continue;
     const int bytes = im.dtype == HRRM_U8 ? 1 : 2;
-    const TileConfig t = ctx->tile_for(bytes, 2, im.r, false, im.width, im.height, 1);
+    const TileConfig t = ctx->tile_for(bytes, 2, im.r, false, im.width, im.height, 1, false);
     BatchImage b{};
     MedianArgs& a = b.args;
     a.src = im.src;

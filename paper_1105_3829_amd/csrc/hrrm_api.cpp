@@ -43,39 +43,52 @@ const char* last_error() { return g_err.c_str(); }
 // ---- tile table ------------------------------------------------------------
 
 TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
-                        int64_t d) {
+                        int64_t d, bool fill_gpu) {
   TileConfig t{};
   t.tiered_u8 = 1;  // the radix-16 tiered kernel is also the faster one for 8-bit data
-  const bool tiered = true;
   const int span = 2 * r + 1;
   t.min_group = 2;
-  // tiered storage: the wave's window counts of one tier come from cooperative
-  // prefix sums (one per subtree the wave touches, about 170 instructions each)
-  // or from per-lane sums over the 2r+1 columns (about 6.5 per column); take the
-  // prefix sums while they are cheaper
-  t.max_groups = tiered ? std::max(1, (int)((6.5 * span + 40) / 170)) : 64;
-  (void)bytes;
   t.nslots = 0;
-  t.lds_budget = 80 * 1024;
-  t.raw_window = 49;  // r <= 3 (2-D) and r = 1 (3-D): deeper tiers counted raw
-  // Enough workgroups to fill 256 CUs several times over, while keeping the
-  // per-segment start-up (2r+1 rows inserted per column) small against the
-  // rows a segment produces.
+  t.lds_budget = 80 * 1024;  // two workgroups per CU
+  // 16-bit windows of at most 49 values (r <= 3 in 2-D, r = 1 in 3-D) count
+  // their deeper tiers from the raw values; 8-bit trees are shallow enough
+  // that held subtrees always win
+  t.raw_window = bytes == 2 ? 49 : 0;
   const int64_t strips = (w + kBlock - 1) / kBlock;
-  const int64_t want_wg = 2048;
-  int64_t rows = (strips * h * d) / want_wg;
-  const int64_t min_rows = std::max<int64_t>(16, 2 * r + 1);
-  rows = std::max<int64_t>(rows, min_rows);
+  int64_t rows;
+  if (dims == 2) {
+    // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..100):
+    // cooperative prefix sums pay off for up to 1, 2 or 4 distinct subtrees
+    // per wave as the window widens; short segments suit wide 16-bit windows,
+    // whose deep tiers are expensive enough that more, smaller tiles balance
+    // the CUs better than the repeated start-up (2r+1 rows per column) costs.
+    t.max_groups = r <= 7 ? 0 : r <= 11 ? 1 : r <= 31 ? 2 : 4;
+    if (bytes == 2)
+      rows = r <= 3 ? 32 : r <= 5 ? 64 : r <= 31 ? 48 : r <= 63 ? 24 : 8;
+    else
+      rows = r <= 2 ? 32 : 128;
+  } else {
+    // per-lane sums cost about 6.5 instructions per column, a cooperative
+    // prefix sum about 170: take prefix sums while they are cheaper
+    t.max_groups = std::max(1, (int)((6.5 * span + 40) / 170));
+    rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
+  }
+  // an image filtered on its own keeps at least ~1024 tiles (four per
+  // workgroup slot of the GPU) when it allows it; in a batch the other images
+  // fill the GPU
+  const int64_t want = 1024;
+  const int64_t fill = (strips * h * d + want - 1) / want;
+  if (fill_gpu && strips * ((h + rows - 1) / rows) * d < want)
+    rows = std::max<int64_t>(8, std::min(rows, fill));
   rows = std::min<int64_t>(rows, 512);
   t.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(rows, h));
-  (void)dims;
   (void)adaptive;
   return t;
 }
 
 TileConfig Context::tile_for(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
-                             int64_t d) const {
-  TileConfig t = default_tile(bytes, dims, r, adaptive, w, h, d);
+                             int64_t d, bool fill_gpu) const {
+  TileConfig t = default_tile(bytes, dims, r, adaptive, w, h, d, fill_gpu);
   for (const auto& e : tuned) {
     if (e.bytes == bytes && e.dims == dims && e.r == r && e.adaptive == (int)adaptive) {
       TileConfig u = e.cfg;

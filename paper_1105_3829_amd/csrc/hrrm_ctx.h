@@ -40,8 +40,9 @@ struct Context {
   // batched launches (persistent kernel), one entry per stream used
   std::vector<BatchStream> batch;
 
-  TileConfig tile_for(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,
-                      int64_t d) const;
+  // fill_gpu: the image runs on its own, so small images get shorter segments
+  TileConfig tile_for(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h, int64_t d,
+                      bool fill_gpu = true) const;
   int ensure_topology(int bytes, int64_t pixels);
   void release_batch();
   BatchStream* batch_for(hipStream_t s);
@@ -51,7 +52,8 @@ struct Context {
 int fail(int code, const char* fmt, ...);
 int fail_hip(hipError_t e, const char* what);
 void clear_error();
-TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h, int64_t d);
+TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h, int64_t d,
+                        bool fill_gpu = true);
 int validate(const void* src, const void* dst, int dtype, int64_t w, int64_t h, int64_t d,
              int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r, int dims);
 int load_tuning(Context* c, const char* path);
