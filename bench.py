@@ -44,18 +44,21 @@ def workload(name: str, r: int):
     raise SystemExit("unknown workload %s" % name)
 
 
-def lds_work_per_pixel(img) -> tuple:
-    """Algorithmic LDS dword-operations per output pixel of the uniform
-    on-demand method: 2*zbar counter updates (one removal, one insertion per
-    column per row; an update touches the levels where the value's bit is 0)
-    plus 2*d column-counter reads (one entering, one leaving column per level
-    of the descent).  zbar is exact for this input (from its histogram)."""
+def lds_work_per_pixel(img, variant: str = "plain") -> tuple:
+    """Algorithmic LDS dword-operations per output pixel of the uniform method:
+    2*zbar counter updates (one removal, one insertion per column per row; an
+    update touches the levels where the value's bit is 0) plus two
+    column-counter reads (entering and leaving column) per window-tree node
+    brought up to date: the d nodes the descent visits for the on-demand
+    update, all 2^d - 1 nodes for the full update.  zbar is exact for this
+    input (from its histogram)."""
     import numpy as np
     d = 8 * img.dtype.itemsize
     hist = np.bincount(img.ravel(), minlength=1 << d).astype(np.float64)
     ones = np.array([bin(v).count("1") for v in range(1 << d)], dtype=np.float64)
     zbar = d - float((hist * ones).sum() / hist.sum())
-    return 2.0 * zbar + 2.0 * d, zbar, d
+    nodes = (1 << d) - 1 if variant == "full" else d
+    return 2.0 * zbar + 2.0 * nodes, zbar, d
 
 
 def cpu_baseline(img, r: int, seconds_target: float = 10.0):
@@ -227,7 +230,7 @@ def main():
     pixels = h * w
     value = pixels / (ms_per_step * 1e-3) / 1e6
 
-    a_ops, zbar, d = lds_work_per_pixel(img)
+    a_ops, zbar, d = lds_work_per_pixel(img, args.variant)
     lds_bytes_launch = a_ops * 4.0 * pixels
     hbm_bytes_launch = 2.0 * img.dtype.itemsize * pixels
     lds_gbs = lds_bytes_launch / (kernel_ms * 1e-3) / 1e9

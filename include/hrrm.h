@@ -50,13 +50,17 @@ extern "C" {
 
 typedef enum { HRRM_U8 = 1, HRRM_U16 = 2 } hrrm_dtype;
 
-/* Tree topology.  PLAIN: the uniform interval-occurrences tree (Sec. III), each
- * split halves its interval, height = bit depth.  ADAPTIVE: the adaptive tree
- * of Sec. III-C, split so that both children are visited about equally often,
- * estimated from the 1:1 mix of the input's global histogram and the global
- * histogram of its running (box) mean; frequent grey values get short paths.
- * Both give identical output. */
-typedef enum { HRRM_PLAIN = 0, HRRM_ADAPTIVE = 1 } hrrm_variant;
+/* Tree topology and window-update form.  PLAIN: the uniform
+ * interval-occurrences tree (Sec. III), each split halves its interval,
+ * height = bit depth, window counts built on demand for the nodes the descent
+ * visits.  ADAPTIVE: the adaptive tree of Sec. III-C, split so that both
+ * children are visited about equally often, estimated from the 1:1 mix of the
+ * input's global histogram and the global histogram of its running (box) mean;
+ * frequent grey values get short paths.  FULL_UPDATE: the uniform tree with the
+ * unconditional update of the entire window tree at every pixel (Sec. III:
+ * strictly constant work per pixel, one update per node), 8-bit data only
+ * (EUNSUPPORTED for 16-bit).  All give identical output. */
+typedef enum { HRRM_PLAIN = 0, HRRM_ADAPTIVE = 1, HRRM_FULL_UPDATE = 2 } hrrm_variant;
 
 /* Largest supported radius.  2-D: column counts are bytes (<= 2r+1 <= 255).
  * 3-D: a column holds (2r+1)^2 values, also kept in a byte. */
@@ -94,7 +98,8 @@ int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t
  *   r            : radius, 0 <= r <= HRRM_MAX_R_2D (window 2r+1).
  * Errors: EINVAL (null pointer with non-zero size, negative size or r,
  * stride < width, misaligned u16 pointer, overlapping buffers, unknown dtype or
- * variant), EUNSUPPORTED (r > HRRM_MAX_R_2D), ENOMEM, EDEVICE. */
+ * variant), EUNSUPPORTED (r > HRRM_MAX_R_2D; FULL_UPDATE with 16-bit data),
+ * ENOMEM, EDEVICE. */
 int hrrm_median2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,
                   int64_t height, int64_t src_row_stride, int64_t dst_row_stride, int32_t r,
                   hrrm_variant variant, void* hip_stream);
@@ -110,7 +115,8 @@ int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype
                   hrrm_variant variant, void* hip_stream);
 
 /* Running k-th order statistic, 0 <= rank < (2r+1)^2 (Sec. III,
- * get_order_statistic with K = rank; Sec. VI, "other order statistics").
+ * get_order_statistic with K = rank; Sec. VI names order statistics other
+ * than the median as a use of the same descent).
  * rank = 0 is the running minimum, (2r+1)^2-1 the running maximum.
  * drop_levels (PLAIN only, 0..bit depth) stops the descent that many levels
  * above the leaves and returns the lower bound of the last node reached

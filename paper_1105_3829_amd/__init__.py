@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(HERE, "libhrrm.so")
 
 OK, EINVAL, ENOMEM, EUNSUPPORTED, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5
 U8, U16 = 1, 2
-PLAIN, ADAPTIVE = 0, 1
+PLAIN, ADAPTIVE, FULL_UPDATE = 0, 1, 2
 MAX_R_2D, MAX_R_3D = 127, 7
 
 _lib = None
@@ -143,7 +143,9 @@ def _variant_code(v) -> int:
         return PLAIN
     if v in (ADAPTIVE, "adaptive"):
         return ADAPTIVE
-    raise ValueError("variant must be 'plain' or 'adaptive'")
+    if v in (FULL_UPDATE, "full", "full_update"):
+        return FULL_UPDATE
+    raise ValueError("variant must be 'plain', 'adaptive' or 'full'")
 
 
 def _stream_ptr(t, stream) -> int:

@@ -136,6 +136,16 @@ int validate(const void* src, const void* dst, int dtype, int64_t w, int64_t h, 
   return HRRM_OK;
 }
 
+// Variants each entry point accepts: the full window update exists for 8-bit
+// data only (a 16-bit window tree has 65535 nodes per pixel).
+int check_variant(int variant, int dtype) {
+  if (variant != HRRM_PLAIN && variant != HRRM_ADAPTIVE && variant != HRRM_FULL_UPDATE)
+    return fail(HRRM_EINVAL, "unknown variant %d", variant);
+  if (variant == HRRM_FULL_UPDATE && dtype == HRRM_U16)
+    return fail(HRRM_EUNSUPPORTED, "the full window update is implemented for 8-bit data only");
+  return HRRM_OK;
+}
+
 // ---- launch ------------------------------------------------------------------
 
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
@@ -145,10 +155,12 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   const int bytes = dtype == HRRM_U8 ? 1 : 2;
   const int bits = 8 * bytes;
   const bool adaptive = variant == HRRM_ADAPTIVE;
+  const bool full = variant == HRRM_FULL_UPDATE;  // 8-bit only, checked by the callers
   TileConfig t = force ? *force : ctx->tile_for(bytes, dims, r, adaptive, w, h, d);
   if (t.seg_rows <= 0) t.seg_rows = 1;
   t.seg_rows = (int32_t)std::min<int64_t>(t.seg_rows, h);
-  const bool tiered = bytes == 2 || t.tiered_u8 != 0;
+  // the full update needs every node of every column: dense storage
+  const bool tiered = !full && (bytes == 2 || t.tiered_u8 != 0);
 
   MedianArgs a{};
   a.src = src;
@@ -204,7 +216,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
     e = launch_topology(a, bytes, dims, ctx->topo_ws, (TopoNode*)ctx->topo, stream);
     if (e != hipSuccess) return fail_hip(e, "adaptive topology launch");
   }
-  e = launch_median(a, bytes, dims, adaptive, tiered, stream);
+  e = launch_median(a, bytes, dims, adaptive, tiered, full, stream);
   if (e != hipSuccess) return fail_hip(e, "median kernel launch");
   return HRRM_OK;
 }
@@ -306,10 +318,9 @@ int hrrm_rank2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, 
   clear_error();
   Context* c = reinterpret_cast<Context*>(ctx);
   if (!c) return fail(HRRM_EINVAL, "null context");
-  if (variant != HRRM_PLAIN && variant != HRRM_ADAPTIVE)
-    return fail(HRRM_EINVAL, "unknown variant %d", (int)variant);
-  int rc = validate(d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride, 0,
-                    r, 2);
+  int rc = check_variant(variant, dtype);
+  if (rc != HRRM_OK) return rc;
+  rc = validate(d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride, 0, r, 2);
   if (rc != HRRM_OK) return rc;
   const int64_t n = (int64_t)(2 * r + 1) * (2 * r + 1);
   if (rank < 0 || rank >= n) return fail(HRRM_EINVAL, "rank %lld outside 0..%lld", (long long)rank,
@@ -331,10 +342,10 @@ int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype
   clear_error();
   Context* c = reinterpret_cast<Context*>(ctx);
   if (!c) return fail(HRRM_EINVAL, "null context");
-  if (variant != HRRM_PLAIN && variant != HRRM_ADAPTIVE)
-    return fail(HRRM_EINVAL, "unknown variant %d", (int)variant);
-  int rc = validate(d_src, d_dst, dtype, width, height, depth, src_row_stride, src_slice_stride,
-                    dst_row_stride, dst_slice_stride, r, 3);
+  int rc = check_variant(variant, dtype);
+  if (rc != HRRM_OK) return rc;
+  rc = validate(d_src, d_dst, dtype, width, height, depth, src_row_stride, src_slice_stride,
+                dst_row_stride, dst_slice_stride, r, 3);
   if (rc != HRRM_OK) return rc;
   if (width == 0 || height == 0 || depth == 0) return HRRM_OK;
   const int64_t s = 2 * r + 1;

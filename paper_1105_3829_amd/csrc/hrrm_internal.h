@@ -64,10 +64,11 @@ struct TileConfig {
   int32_t raw_window; // windows of at most this many values count deeper tiers raw
 };
 
-// Launch the fused median kernel.  dims = 2 or 3.  Returns hipSuccess or the
-// launch error.
+// Launch the fused median kernel.  dims = 2 or 3; full = update every node of
+// the window tree at every pixel (8-bit dense storage only).  Returns
+// hipSuccess or the launch error.
 hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive, bool tiered,
-                         hipStream_t stream);
+                         bool full, hipStream_t stream);
 
 // LDS bytes a launch with these parameters needs.
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);

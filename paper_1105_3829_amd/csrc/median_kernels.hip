@@ -25,6 +25,12 @@
 // byte each, node-major/column-minor so that 64 lanes reading one node hit 64
 // consecutive bytes.  (16-bit trees use the tiered kernel, median_tiered.hip.)
 //
+// Full-update form (FULL): instead of counting only the nodes the descent
+// visits, every node of the window tree is brought to the current window at
+// every pixel (Sec. III: the unconditional update of the entire window tree,
+// strictly constant work per pixel, 2^d - 1 node updates).  A wave does it as
+// one prefix sum per node; each lane keeps the count of the node it is at.
+//
 // Topology: uniform (each split halves its interval, Sec. III) or adaptive
 // (split points from a table, leaf test at every visit, Sec. III-C).
 #include "hrrm_internal.h"
@@ -73,6 +79,27 @@ __device__ __forceinline__ Step<ADAPT> node_step(const TopoNode* topo, int node,
   return s;
 }
 
+// Window count of counter row `row` (wave-uniform) for every lane: count of
+// the wave's first window plus the running sum of (entering - leaving column).
+// Must be called with all 64 lanes active.
+__device__ __forceinline__ uint32_t scan_count(const uint8_t* __restrict__ cnt, int cp, int row,
+                                               int lx, int span, int lane, int wbase) {
+  const uint8_t* base = cnt + (size_t)row * cp;
+  const uint32_t vout = base[lx];        // column of x - r - 1
+  const uint32_t vin = base[lx + span];  // column of x + r
+  const uint32_t sc = wave_scan((vin << 16) | vout);
+  uint32_t b;
+  if (span <= 64) {
+    b = (uint32_t)readlane((int)(sc & 0xffffu), span - 1);
+  } else {
+    uint32_t e = 0;
+    for (int k = 64 + lane; k < span; k += 64) e += base[wbase + k];
+    const uint32_t es = wave_scan(e);
+    b = (uint32_t)readlane((int)(sc & 0xffffu), 63) + (uint32_t)readlane((int)es, 63);
+  }
+  return b + (sc >> 16) - (sc & 0xffffu);
+}
+
 // Window count of each lane's counter row (lanes with want=true), see the file
 // comment.  Must be called with all 64 lanes active.
 __device__ __forceinline__ uint32_t window_count(const uint8_t* __restrict__ cnt, int cp, int row,
@@ -92,20 +119,7 @@ __device__ __forceinline__ uint32_t window_count(const uint8_t* __restrict__ cnt
       continue;
     }
     ++ng;
-    const uint8_t* base = cnt + (size_t)grow * cp;
-    const uint32_t vout = base[lx];         // column of x - r - 1
-    const uint32_t vin = base[lx + span];   // column of x + r
-    const uint32_t sc = wave_scan((vin << 16) | vout);
-    uint32_t b;
-    if (span <= 64) {
-      b = (uint32_t)readlane((int)(sc & 0xffffu), span - 1);
-    } else {
-      uint32_t e = 0;
-      for (int k = 64 + lane; k < span; k += 64) e += base[wbase + k];
-      const uint32_t es = wave_scan(e);
-      b = (uint32_t)readlane((int)(sc & 0xffffu), 63) + (uint32_t)readlane((int)es, 63);
-    }
-    const uint32_t wl = b + (sc >> 16) - (sc & 0xffffu);
+    const uint32_t wl = scan_count(cnt, cp, grow, lx, span, lane, wbase);
     if ((m >> lane) & 1) w = wl;
   }
   if (direct) {
@@ -145,8 +159,9 @@ __device__ __forceinline__ void column_walk(uint8_t* cnt, int cp, const TopoNode
   }
 }
 
-template <typename T, bool ADAPT, bool D3>
+template <typename T, bool ADAPT, bool D3, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_median_dense(MedianArgs a) {
+  static_assert(!(FULL && ADAPT), "the full update walks the uniform tree");
   extern __shared__ __align__(16) uint8_t lds[];
   const T* __restrict__ src = (const T*)a.src;
   T* __restrict__ dst = (T*)a.dst;
@@ -215,7 +230,31 @@ __global__ __launch_bounds__(kBlock) void k_median_dense(MedianArgs a) {
     uint32_t acc = 0;
     bool done = (x >= a.w) || (stop == 0);
     int res = 0;
-    for (int k = 0; k < maxdepth; ++k) {
+    if constexpr (FULL) {
+      // level k holds the nodes with heap indices 2^k .. 2^(k+1)-1; all of them
+      // are brought to this pixel's window, the lane keeps its own node's count
+      for (int k = 0; k < stop; ++k) {
+        uint32_t wl = 0;
+        for (int q = 1 << k; q < (2 << k); ++q) {
+          const uint32_t w = scan_count(cnt, cp, q - 1, lx, span, lane, wv * 64);
+          wl = node == q ? w : wl;
+        }
+        if (!done) {
+          if (acc + wl > K) {
+            node = 2 * node;
+          } else {
+            acc += wl;
+            lo += 1 << (bits - 1 - k);
+            node = 2 * node + 1;
+          }
+          if (k + 1 >= stop) {
+            done = true;
+            res = lo;
+          }
+        }
+      }
+    }
+    for (int k = 0; k < (FULL ? 0 : maxdepth); ++k) {
       const bool act = !done;
       if (ballot(act) == 0) break;
       const Step<ADAPT> s = node_step<ADAPT>(topo, node, lo, depth, bits);
@@ -266,9 +305,9 @@ __global__ __launch_bounds__(kBlock) void k_median_dense(MedianArgs a) {
   }
 }
 
-template <bool ADAPT, bool D3>
+template <bool ADAPT, bool D3, bool FULL>
 hipError_t launch_dense(const MedianArgs& a, size_t lds, hipStream_t stream) {
-  auto kern = k_median_dense<uint8_t, ADAPT, D3>;
+  auto kern = k_median_dense<uint8_t, ADAPT, D3, FULL>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -294,14 +333,19 @@ size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp
 }
 
 hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive, bool tiered,
-                         hipStream_t stream) {
+                         bool full, hipStream_t stream) {
   const size_t lds = median_lds_bytes(bytes, adaptive, tiered, a.ncols, a.cp, a.nslots);
   if (tiered) return launch_median_tiered(a, bytes, dims, adaptive, lds, stream);
   if (bytes != 1) return hipErrorInvalidValue;  // dense storage holds 8-bit trees only
-  if (adaptive) return dims == 3 ? launch_dense<true, true>(a, lds, stream)
-                                 : launch_dense<true, false>(a, lds, stream);
-  return dims == 3 ? launch_dense<false, true>(a, lds, stream)
-                   : launch_dense<false, false>(a, lds, stream);
+  if (full) {
+    if (adaptive) return hipErrorInvalidValue;
+    return dims == 3 ? launch_dense<false, true, true>(a, lds, stream)
+                     : launch_dense<false, false, true>(a, lds, stream);
+  }
+  if (adaptive) return dims == 3 ? launch_dense<true, true, false>(a, lds, stream)
+                                 : launch_dense<true, false, false>(a, lds, stream);
+  return dims == 3 ? launch_dense<false, true, false>(a, lds, stream)
+                   : launch_dense<false, false, false>(a, lds, stream);
 }
 
 }  // namespace hrrm

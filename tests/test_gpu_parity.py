@@ -165,19 +165,108 @@ def test_repeatable(hrrm):
         assert np.array_equal(to_host(hrrm.median2d(d, 9)), a)
 
 
-def test_c1_full_size_sampled(hrrm):
-    # the headline workload at full size: u16 4096^2, r = 15, both variants;
-    # the oracle checks 20000 sampled pixels plus full borders of rows/columns
+@pytest.mark.parametrize("r", [5, 15, 50])
+def test_c1_full_size_sampled(hrrm, r):
+    # the headline workload at full size: u16 4096^2, both variants, default
+    # tiles (the launch the benchmark times); the oracle checks 20000 sampled
+    # pixels plus sampled pixels of the first and last rows
     img = datagen.xray_u16(4096, 4096, seed=1)
     d = to_dev(img)
     g = np.random.default_rng(1)
     ys = np.concatenate([g.integers(0, 4096, 20000), np.zeros(512, int), np.full(512, 4095)])
     xs = np.concatenate([g.integers(0, 4096, 20000), g.integers(0, 4096, 1024)])
-    want = oracle.rank2d_at(img, 15, xs, ys)
+    want = oracle.rank2d_at(img, r, xs, ys)
     for variant in ("plain", "adaptive"):
-        announce("c1 full", variant)
-        got = to_host(hrrm.median2d(d, 15, variant=variant))
+        announce("c1 full", "r=%d" % r, variant)
+        got = to_host(hrrm.median2d(d, r, variant=variant))
         assert np.array_equal(got[ys, xs], want), variant
+
+
+@pytest.mark.parametrize("r", [1, 16, 100])
+def test_c2_full_size_sampled(hrrm, r):
+    # u8 8192^2 low-key image at full size (plain and full-update forms)
+    img = datagen.lowkey_u8(8192, 8192, seed=2)
+    d = to_dev(img)
+    g = np.random.default_rng(2)
+    n = 4000 if r == 100 else 20000
+    ys = np.concatenate([g.integers(0, 8192, n), np.zeros(256, int), np.full(256, 8191)])
+    xs = np.concatenate([g.integers(0, 8192, n), g.integers(0, 8192, 512)])
+    want = oracle.rank2d_at(img, r, xs, ys)
+    for variant in ("plain", "full"):
+        announce("c2 full", "r=%d" % r, variant)
+        got = to_host(hrrm.median2d(d, r, variant=variant))
+        assert np.array_equal(got[ys, xs], want), variant
+
+
+def test_c3_full_size_sampled(hrrm):
+    # u16 512x512x256 volume with impulses at full size, r = 7
+    vol = datagen.xray_volume_u16(256, 512, 512, seed=3)
+    d = to_dev(vol)
+    g = np.random.default_rng(3)
+    zs = np.concatenate([g.integers(0, 256, 3000), np.zeros(200, int), np.full(200, 255)])
+    ys = g.integers(0, 512, zs.size)
+    xs = g.integers(0, 512, zs.size)
+    want = oracle.rank3d_at(vol, 7, xs, ys, zs)
+    announce("c3 full r=7")
+    got = to_host(hrrm.median3d(d, 7))
+    assert np.array_equal(got[zs, ys, xs], want)
+
+
+@pytest.mark.parametrize("r", [0, 1, 5, 31, 33, 64, 100])
+def test_full_update_u8(hrrm, r):
+    # the unconditional whole-window-tree update gives the same medians
+    img = datagen.uniform_u8(120, 300, seed=100 + r) if r % 2 else datagen.lowkey_u8(120, 300,
+                                                                                      seed=100 + r)
+    _check2d(hrrm, img, r, "full")
+
+
+def test_full_update_rank_3d_and_errors(hrrm):
+    import torch
+    img = datagen.uniform_u8(70, 280, seed=110)
+    r = 3
+    n = (2 * r + 1) ** 2
+    for k, drop in ((0, 0), (n // 3, 0), (n - 1, 0), ((n - 1) // 2, 3)):
+        announce("full rank", k, drop)
+        got = to_host(hrrm.rank2d(to_dev(img), r, k, drop_levels=drop, variant="full"))
+        assert np.array_equal(got, oracle.rank2d(img, r, k, drop_bits=drop)), (k, drop)
+    vol = np.stack([datagen.lowkey_u8(30, 270, seed=111 + z) for z in range(5)])
+    for r3 in (1, 3):
+        announce("full 3d", r3)
+        got = to_host(hrrm.median3d(to_dev(vol), r3, variant="full"))
+        assert np.array_equal(got, oracle.median3d(vol, r3)), r3
+    u16 = to_dev(datagen.xray_u16(20, 30, seed=112))
+    with pytest.raises(hrrm.HrrmError):
+        hrrm.median2d(u16, 2, variant="full")
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("bits_free", [0, 1, 3, 5, 9])
+def test_u16_common_prefix(hrrm, bits_free):
+    # 16-bit values confined to an aligned or unaligned band: the tile's common
+    # prefix fixes many top levels (all of them for a constant image)
+    g = np.random.default_rng(120 + bits_free)
+    for base in (0x1230, 0xFFFF - (1 << bits_free) + 1, 0x7FF0):
+        img = (base + g.integers(0, 1 << bits_free, size=(90, 300))).astype(np.uint16)
+        for r in (1, 4, 12):
+            _check2d(hrrm, img, r)
+        n = 81
+        for drop in (2, 13, 16):
+            announce("prefix drop", bits_free, hex(base), drop)
+            got = to_host(hrrm.rank2d(to_dev(img), 4, (n - 1) // 2, drop_levels=drop))
+            assert np.array_equal(got, oracle.rank2d(img, 4, None, drop_bits=drop)), drop
+
+
+def test_u16_mixed_prefix_tiles(hrrm):
+    # tiles with different common prefixes side by side (constant, narrow band,
+    # full range), and a band crossing a power-of-two boundary
+    g = np.random.default_rng(130)
+    img = np.empty((140, 800), np.uint16)
+    img[:, :260] = 4000
+    img[:, 260:520] = 0x8000 + g.integers(0, 8, size=(140, 260))
+    img[:, 520:] = g.integers(0, 65536, size=(140, 280))
+    img[100:, :] = (0x7FFC + g.integers(0, 8, size=(40, 800))).astype(np.uint16)
+    for r in (2, 7, 20):
+        _check2d(hrrm, img, r)
 
 
 def test_validation_errors(hrrm):
