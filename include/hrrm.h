@@ -114,6 +114,22 @@ int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype
                   int64_t dst_row_stride, int64_t dst_slice_stride, int32_t r,
                   hrrm_variant variant, void* hip_stream);
 
+/* Running median of one frame of an image sequence with the adaptive tree
+ * (Sec. III-C: for video, the median distribution of the previous frame can
+ * stand for where the order-statistic descents go).  The topology is built
+ * from the 1:1 mix of this frame's global histogram and the global histogram
+ * of d_estimate - typically the previous frame's median output, left on the
+ * device - instead of the running-mean histogram; d_estimate = NULL falls back
+ * to the running mean (first frame).  d_estimate is a width x height image of
+ * `dtype` with row stride est_row_stride (elements); it may alias d_dst (it is
+ * read completely before the frame's output is written, in stream order).
+ * Output is identical to hrrm_median2d.  Errors as hrrm_median2d, plus EINVAL
+ * for est_row_stride < width or a misaligned 16-bit estimate. */
+int hrrm_median2d_video(hrrm_ctx ctx, const void* d_src, void* d_dst, const void* d_estimate,
+                        hrrm_dtype dtype, int64_t width, int64_t height, int64_t src_row_stride,
+                        int64_t dst_row_stride, int64_t est_row_stride, int32_t r,
+                        void* hip_stream);
+
 /* Running k-th order statistic, 0 <= rank < (2r+1)^2 (Sec. III,
  * get_order_statistic with K = rank; Sec. VI names order statistics other
  * than the median as a use of the same descent).

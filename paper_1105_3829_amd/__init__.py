@@ -85,6 +85,8 @@ def lib():
                 "hrrm_median3d": ([vp, vp, vp, i32, i64, i64, i64, i64, i64, i64, i64, i32, i32, vp],
                                   i32),
                 "hrrm_rank2d": ([vp, vp, vp, i32, i64, i64, i64, i64, i32, i64, i32, i32, vp], i32),
+                "hrrm_median2d_video": ([vp, vp, vp, vp, i32, i64, i64, i64, i64, i64, i32, vp],
+                                        i32),
                 "hrrm_median2d_batched": ([vp, ctypes.POINTER(_Image), i32, vp], i32),
                 "hrrm_batch_capacity": ([], i32),
                 "hrrm_autotune": ([vp, vp, i32, i32, i32, i64, i64, i64, cp, ctypes.POINTER(i32)],
@@ -206,6 +208,24 @@ class Context:
         check(lib().hrrm_rank2d(self._h, src.data_ptr(), out.data_ptr(), _dtype_code(src), w, h,
                                 src.stride(0), out.stride(0), r, k, drop_levels,
                                 _variant_code(variant), _stream_ptr(src, stream)))
+        return out
+
+    def median2d_video(self, src, r: int, estimate=None, out=None, stream=None):
+        """Adaptive-tree median of one frame; `estimate` (same shape and dtype,
+        e.g. the previous frame's output) replaces the running-mean histogram
+        in the topology; None = running mean.  `out` may be `estimate`."""
+        if src.dim() != 2 or src.stride(1) != 1:
+            raise ValueError("median2d_video takes a (H, W) tensor with contiguous rows")
+        out = self._out(src, out)
+        h, w = src.shape
+        ep, es = None, 0
+        if estimate is not None:
+            if estimate.shape != src.shape or estimate.dtype != src.dtype or estimate.stride(1) != 1:
+                raise ValueError("estimate must match src in shape and dtype, rows contiguous")
+            ep, es = estimate.data_ptr(), estimate.stride(0)
+        check(lib().hrrm_median2d_video(self._h, src.data_ptr(), out.data_ptr(), ep,
+                                        _dtype_code(src), w, h, src.stride(0), out.stride(0), es,
+                                        r, _stream_ptr(src, stream)))
         return out
 
     def median3d(self, src, r: int, variant="plain", out=None, stream=None):
@@ -405,13 +425,18 @@ def median3d(src, r: int, variant="plain", out=None, stream=None):
     return context(_dev(src)).median3d(src, r, variant, out, stream)
 
 
+def median2d_video(src, r: int, estimate=None, out=None, stream=None):
+    return context(_dev(src)).median2d_video(src, r, estimate, out, stream)
+
+
 def median2d_batched(srcs, radii, outs=None, stream=None):
     return context(_dev(srcs[0])).median2d_batched(srcs, radii, outs, stream)
 
 
 EXPORTED_SYMBOLS: List[str] = [
     "hrrm_last_error", "hrrm_version", "hrrm_ctx_create", "hrrm_ctx_destroy", "hrrm_ctx_reserve",
-    "hrrm_median2d", "hrrm_median3d", "hrrm_rank2d", "hrrm_median2d_batched",
+    "hrrm_median2d", "hrrm_median3d", "hrrm_rank2d", "hrrm_median2d_video",
+    "hrrm_median2d_batched",
     "hrrm_batch_capacity", "hrrm_autotune", "hrrm_load_tuning", "hrrm_save_tuning",
     "hrrm_set_tile_config",
     "hrrm_get_tile_config", "hrrm_server_create",

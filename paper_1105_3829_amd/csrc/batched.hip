@@ -103,7 +103,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     a.segs = (int32_t)((im.height + a.seg_rows - 1) / a.seg_rows);
     a.ncols = kBlock + 2 * im.r + 1;
     a.cp = (a.ncols + 3) & ~3;
-    const size_t meta = tiered_meta_bytes(im.r) + 16;
+    const size_t meta = tiered_meta_bytes(im.r, bytes) + 16;
     const size_t slot_bytes = (size_t)a.cp * 16;
     int ns = kBatchLds > meta ? (int)((kBatchLds - meta) / slot_bytes) : 0;
     if (t.nslots > 0) ns = std::min(ns, t.nslots);

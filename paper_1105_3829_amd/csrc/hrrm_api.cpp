@@ -151,7 +151,7 @@ int check_variant(int variant, int dtype) {
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
                int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,
                int64_t rank, int drop, int variant, int dims, hipStream_t stream,
-               const TileConfig* force) {
+               const TileConfig* force, const void* est, int64_t est_rs) {
   const int bytes = dtype == HRRM_U8 ? 1 : 2;
   const int bits = 8 * bytes;
   const bool adaptive = variant == HRRM_ADAPTIVE;
@@ -213,7 +213,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
     int rc = ctx->ensure_topology(bytes, w * h * a.d);
     if (rc != HRRM_OK) return rc;
     a.topo = (const TopoNode*)ctx->topo;
-    e = launch_topology(a, bytes, dims, ctx->topo_ws, (TopoNode*)ctx->topo, stream);
+    e = launch_topology(a, bytes, dims, ctx->topo_ws, (TopoNode*)ctx->topo, stream, est, est_rs);
     if (e != hipSuccess) return fail_hip(e, "adaptive topology launch");
   }
   e = launch_median(a, bytes, dims, adaptive, tiered, full, stream);
@@ -333,6 +333,27 @@ int hrrm_rank2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, 
   if (width == 0 || height == 0) return HRRM_OK;
   return run_filter(c, d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride,
                     0, r, rank, drop_levels, variant, 2, (hipStream_t)hip_stream, nullptr);
+}
+
+int hrrm_median2d_video(hrrm_ctx ctx, const void* d_src, void* d_dst, const void* d_estimate,
+                        hrrm_dtype dtype, int64_t width, int64_t height, int64_t src_row_stride,
+                        int64_t dst_row_stride, int64_t est_row_stride, int32_t r,
+                        void* hip_stream) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  int rc = validate(d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride, 0,
+                    r, 2);
+  if (rc != HRRM_OK) return rc;
+  if (width == 0 || height == 0) return HRRM_OK;
+  if (d_estimate) {
+    if (est_row_stride < width) return fail(HRRM_EINVAL, "estimate row stride smaller than width");
+    if (dtype == HRRM_U16 && (((uintptr_t)d_estimate) & 1))
+      return fail(HRRM_EINVAL, "uint16 estimate not 2-byte aligned");
+  }
+  return run_filter(c, d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride,
+                    0, r, ((int64_t)(2 * r + 1) * (2 * r + 1) - 1) / 2, 0, HRRM_ADAPTIVE, 2,
+                    (hipStream_t)hip_stream, nullptr, d_estimate, est_row_stride);
 }
 
 int hrrm_median3d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, int64_t width,

@@ -60,9 +60,10 @@ int load_tuning(Context* c, const char* path);
 int save_tuning(const Context* c, const char* path);
 int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t stream,
                 bool use_graph);
+// est / est_rs: optional estimate image for the adaptive topology (2-D)
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
                int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,
                int64_t rank, int drop, int variant, int dims, hipStream_t stream,
-               const TileConfig* force);
+               const TileConfig* force, const void* est = nullptr, int64_t est_rs = 0);
 
 }  // namespace hrrm

@@ -12,9 +12,18 @@ constexpr int kTierNodes = (1 << kTierLevels) - 1;  // left-node counters per ti
 constexpr int kDenseNodes = 255;     // left-node counters of a full 8-bit tree
 constexpr int kHash = 128;           // slot hash-table entries (power of two)
 constexpr int kMaxSlots = 64;        // tier slots per workgroup, slot 0 included
-constexpr int kMaxMiss = kBlock;     // misses collected per round
 constexpr int kLdsLimit = 160 * 1024;
 constexpr int kRawWindow = 81;       // (2r+1)^D up to this: missing subtrees counted raw
+
+// Bytes of one wave's scratch area in the tiered kernel: the column vectors
+// of a subtree for the wave's 64 + 2r + 1 columns (16 bytes each), or the
+// raw-count histograms (8 x 64 dwords) plus one staged window row of
+// 64 + 2r 16-bit values, whichever is larger; 16-byte aligned.
+__host__ __device__ constexpr size_t wave_scratch_bytes(int r) {
+  const size_t cols = (size_t)(64 + 2 * r + 1) * 16;
+  const size_t raw = 8 * 64 * 4 + (size_t)(64 + 2 * r) * 2;
+  return ((cols > raw ? cols : raw) + 15) & ~(size_t)15;
+}
 
 // Adaptive topology node.  Internal nodes are numbered 0..2^d-2 (root 0).
 // A child >= 0 is an internal node; a child < 0 is the leaf holding grey value
@@ -73,9 +82,10 @@ hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive
 // LDS bytes a launch with these parameters needs.
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);
 
-// Tiered-kernel LDS bytes besides the slots, for radius r; adaptive trees add
-// tiered_topo_bytes(nslots) for the held subtrees' topology.
-size_t tiered_meta_bytes(int r);
+// Tiered-kernel LDS bytes besides the slots, for radius r and element size
+// `bytes` (1 or 2); adaptive trees add tiered_topo_bytes(nslots) for the held
+// subtrees' topology.
+size_t tiered_meta_bytes(int r, int bytes);
 size_t tiered_topo_bytes(int nslots);
 
 // Persistent batched launch (zeroes *d_counter first, then runs `grid`
@@ -87,10 +97,11 @@ hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32
 
 // Adaptive topology pre-pass (Sec. III-C).  Builds `topo` (2^bits - 1 nodes)
 // from the input's global histogram mixed 1:1 with the histogram of its
-// clamp-to-edge box mean over the same window.  ws must hold
-// topology_workspace_bytes(bits, pixels) bytes.
+// clamp-to-edge box mean over the same window, or, when `est` is given, with
+// the histogram of that w x h estimate image (row stride est_rs; 2-D).  ws
+// must hold topology_workspace_bytes(bits, pixels) bytes.
 size_t topology_workspace_bytes(int bits, int64_t pixels);
 hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* ws, TopoNode* topo,
-                           hipStream_t stream);
+                           hipStream_t stream, const void* est = nullptr, int64_t est_rs = 0);
 
 }  // namespace hrrm

@@ -322,10 +322,9 @@ hipError_t launch_median_tiered(const MedianArgs& a, int bytes, int dims, bool a
                                 size_t lds, hipStream_t stream);
 
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots) {
-  (void)bytes;
   // ncols = 256 + 2r + 1
   if (tiered)
-    return (((size_t)nslots * cp * 16 + 15) & ~(size_t)15) + tiered_meta_bytes((ncols - 257) / 2) +
+    return (((size_t)nslots * cp * 16 + 15) & ~(size_t)15) + tiered_meta_bytes((ncols - 257) / 2, bytes) +
            (adaptive ? tiered_topo_bytes(nslots) : 0);
   size_t b = ((size_t)kDenseNodes * cp + 15) & ~(size_t)15;
   if (adaptive) b += sizeof(TopoNode) * (kDenseNodes + 1);

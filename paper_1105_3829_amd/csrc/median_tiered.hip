@@ -28,9 +28,15 @@
 //  * direct: each lane sums the 2r+1 column vectors of its own window (the
 //    paper's non-elementary catch-up), used when the wave's pixels are spread
 //    over several subtrees.
-// When every slot already serves the current row, the wave builds the missing
-// subtree's column vectors for just its own 64+2r columns from the raw window
-// values in a per-wave scratch area and sums those instead.
+// A subtree no slot holds (every slot serves the current row, or too few lanes
+// want it to be worth a slot) is counted by the wave itself: for a few such
+// subtrees the wave builds each one's column vectors for just its own 64+2r
+// columns from the raw window values in a per-wave scratch area and sums
+// those; when its lanes want many different subtrees (medians that change fast
+// along the row, as at edges) every such lane instead histograms the raw
+// values of its own window that fall in its subtree, one LDS-staged window row
+// at a time - the paper's non-elementary update from scratch, O(window) per
+// pixel, with no slot traffic.
 //
 // Uniform trees locate tier roots arithmetically (prefix of the value) and map
 // them to slots with a direct table; adaptive trees (Sec. III-C) follow the
@@ -41,13 +47,17 @@
 namespace hrrm {
 namespace {
 
-constexpr int kMissCap = 64;
+constexpr int kMissGroups = 8;  // subtree groups per wave and round offered to the slots
+constexpr int kMissCap = kMissGroups * kWaves;  // misses queued per round
+constexpr int kSlotLanes = 4;   // lanes that must share a subtree to claim a slot in a wave
+                                // that wants more than kMissGroups different subtrees
 constexpr int kSmap = 16 + 256 + 4096;  // roots of tiers 2..4 of a 16-bit uniform tree
 constexpr uint32_t kNone = 0xffu;
 
-struct TierState {
+template <int NSMAP>
+struct TierStateT {
   uint4 lut[16];                 // uniform insertion masks of a 4-level subtree
-  uint8_t smap[kSmap];           // uniform: tier-root key -> slot (kNone = absent)
+  uint8_t smap[NSMAP];           // uniform: tier-root key -> slot (kNone = absent)
   uint32_t ht[kHash];            // adaptive: (node + 1) << 8 | slot, 0 = empty
   int32_t key[kMaxSlots], lo[kMaxSlots], hi[kMaxSlots], dep[kMaxSlots], stamp[kMaxSlots];
   int32_t miss_n[3];
@@ -56,8 +66,11 @@ struct TierState {
   int32_t pad;
   uint32_t vand, vor;            // AND / OR of every value the tile reads
   int32_t miss[kMissCap][4];     // key, lo, hi, depth of a subtree root nobody holds
-  int32_t reb[kMaxSlots][4];     // slot, key, lo, depth of a slot to rebuild
+  int32_t reb[kMissCap][4];      // slot, key, lo, depth of a slot to rebuild
 };
+// 8-bit trees have one tier below the first: 16 possible subtree roots
+template <typename T>
+using TierState = TierStateT<sizeof(T) == 1 ? 16 : kSmap>;
 
 __device__ __forceinline__ uint32_t ht_hash(int key) {
   return ((uint32_t)key * 2654435761u) >> 25;  // 7 bits for kHash = 128
@@ -278,7 +291,7 @@ __device__ __forceinline__ void direct_counts(uint32_t (&W)[8], const uint8_t* s
 // later rows.
 template <typename T, bool ADAPT, bool D3>
 __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict__ src,
-                                              const MedianArgs& a, const TierState* ts,
+                                              const MedianArgs& a, const TierState<T>* ts,
                                               const TopoNode* topo, int64_t x0w, int64_t y,
                                               int64_t z, int lane, int span, int node, int rlo,
                                               int rhi, int rdep) {
@@ -309,7 +322,7 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
 // small windows this is cheaper than building the subtree's column vectors).
 template <typename T, bool ADAPT, bool D3>
 __device__ __forceinline__ void raw_counts(uint32_t (&W)[8], const T* __restrict__ src,
-                                           const MedianArgs& a, const TierState* ts,
+                                           const MedianArgs& a, const TierState<T>* ts,
                                            const TopoNode* topo, int64_t x, int64_t y, int64_t z,
                                            int node, int rlo, int rhi, int rdep) {
   constexpr int bits = 8 * sizeof(T);
@@ -348,18 +361,100 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Uniform tree: window counts of each needing lane's own tier subtree (root at
+// depth dep, interval starting at lo) from the raw window values.  The wave
+// stages every window row (64 + 2r values) in LDS once; each needing lane adds
+// the values of its window that fall in its interval to a private 16-bin
+// histogram of the four value bits below dep; the 15 left-node counts follow
+// from the bins.  All 64 lanes must call it; buf is the wave's scratch area.
+template <typename T, bool D3>
+__device__ __forceinline__ void raw_wave(uint32_t (&W)[8], bool need, int lo, int dep,
+                                         uint8_t* buf, const T* __restrict__ src,
+                                         const MedianArgs& a, int64_t x0w, int64_t y, int64_t z,
+                                         int lane) {
+  constexpr int bits = 8 * sizeof(T);
+  const int r = a.r, span = 2 * r + 1, zr = D3 ? r : 0;
+  uint32_t* hist = (uint32_t*)buf;  // bins 2k, 2k+1 of lane l: 16-bit halves of hist[k * 64 + l]
+  T* stage = (T*)(buf + 8 * 64 * 4);
+  const uint32_t width = need ? 1u << (bits - dep) : 0u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) hist[k * 64 + lane] = 0;
+  for (int dz = -zr; dz <= zr; ++dz) {
+    const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+    for (int dy = -r; dy <= r; ++dy) {
+      const T* rowp = src + zz * a.sss + clampi(y + dy, a.h - 1) * a.srs;
+      for (int c = lane; c < 64 + 2 * r; c += 64) stage[c] = rowp[clampi(x0w - r + c, a.w - 1)];
+      wave_sync_lds();
+      if (need) {
+        for (int dx = 0; dx < span; ++dx) {
+          const uint32_t v = stage[lane + dx];
+          if (v - (uint32_t)lo < width) {
+            const int bn = nib((int)v, dep, bits);
+            atomicAdd(&hist[(bn >> 1) * 64 + lane], 1u << ((bn & 1) * 16));
+          }
+        }
+      }
+      wave_sync_lds();
+    }
+  }
+  if (need) {
+    uint32_t bin[16];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t hk = hist[k * 64 + lane];
+      bin[2 * k] = hk & 0xffffu;
+      bin[2 * k + 1] = hk >> 16;
+    }
+    // left-node counts in heap order (node q = heap position q + 1)
+    uint32_t c[15];
+    c[0] = bin[0] + bin[1] + bin[2] + bin[3] + bin[4] + bin[5] + bin[6] + bin[7];
+    c[1] = bin[0] + bin[1] + bin[2] + bin[3];
+    c[2] = bin[8] + bin[9] + bin[10] + bin[11];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[3 + i] = bin[4 * i] + bin[4 * i + 1];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[7 + i] = bin[2 * i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) W[i] = 0;
+#pragma unroll
+    for (int q = 0; q < 15; ++q) W[2 * (q >> 2) + (q & 1)] |= c[q] << (16 * ((q >> 1) & 1));
+  }
+  wave_sync_lds();  // the scratch area is reused right after
+}
+
 // Slot assignment for this round's misses (thread 0): least recently used
 // slots not used by the current row are replaced.  Adaptive trees also drop the
 // held subtrees below a replaced slot (their updates walk down from the top and
 // stop at the first subtree no slot holds).
-template <bool ADAPT>
-__device__ void assign_slots(TierState* ts, int nmiss, int stamp, int nslots, TopoNode* stopo,
-                             const TopoNode* topo) {
+// Adaptive trees: are all tier subtrees above the one rooted at `key` (depth
+// dep, interval starting at lo) held?  Column updates walk down from the top
+// and stop at the first subtree no slot holds, so a subtree below one that is
+// not held would go stale.  The path follows lo through the topology.
+template <typename TS>
+__device__ __forceinline__ bool ancestors_held(const TS* ts, const TopoNode* topo, int root,
+                                               int lo, int dep) {
+  int nd = root;
+  for (int d = kTierLevels; d < dep; d += kTierLevels) {
+    for (int k = 0; k < kTierLevels && nd >= 0; ++k) {
+      const TopoNode t = topo[nd];
+      nd = lo < t.split ? t.left : t.right;
+    }
+    if (nd < 0 || ht_find(ts->ht, nd) < 0) return false;
+  }
+  return true;
+}
+
+template <bool ADAPT, typename TS>
+__device__ void assign_slots(TS* ts, int nmiss, int stamp, int nslots, TopoNode* stopo,
+                             const TopoNode* topo, int root) {
   int nreb = 0;
   for (int i = 0; i < nmiss; ++i) {
     const int key = ts->miss[i][0];
     const bool held = ADAPT ? ht_find(ts->ht, key) >= 0 : ts->smap[key] != kNone;
     if (held) continue;  // duplicate from another wave
+    if constexpr (ADAPT) {
+      if (!ancestors_held(ts, topo, root, ts->miss[i][1], ts->miss[i][3])) continue;
+    }
     int victim = -1, best = 0x7fffffff;
     for (int s = 1; s < nslots; ++s) {
       const int st = ts->stamp[s];
@@ -426,13 +521,14 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   const int64_t ye = yb + a.seg_rows < a.h ? yb + a.seg_rows : a.h;
 
   uint8_t* slots = lds;
-  TierState* ts = (TierState*)(lds + align16((size_t)a.nslots * cp16));
+  using TS = TierState<T>;
+  TS* ts = (TS*)(lds + align16((size_t)a.nslots * cp16));
   // per-wave scratch of (64 + 2r + 1) column vectors for subtrees no slot holds
-  uint8_t* scr = lds + align16((size_t)a.nslots * cp16) + align16(sizeof(TierState)) +
-                 (size_t)wv * (64 + span) * 16;
+  uint8_t* scr = lds + align16((size_t)a.nslots * cp16) + align16(sizeof(TS)) +
+                 (size_t)wv * wave_scratch_bytes(r);
   // adaptive: topology of each held subtree (16 entries per slot) after the scratch
   TopoNode* stopo = (TopoNode*)(lds + align16((size_t)a.nslots * cp16) +
-                                align16(sizeof(TierState)) + (size_t)kWaves * (64 + span) * 16);
+                                align16(sizeof(TS)) + (size_t)kWaves * wave_scratch_bytes(r));
   const int root = ADAPT ? topo[(1 << bits) - 1].split : 1;
   const int maxv = (1 << bits) - 1;
   const int ntiers = (bits + kTierLevels - 1) / kTierLevels;
@@ -449,7 +545,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   if constexpr (ADAPT) {
     for (int i = tid; i < kHash; i += kBlock) ts->ht[i] = 0;
   } else {
-    for (int i = tid; i < kSmap; i += kBlock) ts->smap[i] = (uint8_t)kNone;
+    for (int i = tid; i < (int)sizeof(ts->smap); i += kBlock) ts->smap[i] = (uint8_t)kNone;
   }
   for (int s = tid; s < kMaxSlots; s += kBlock) {
     ts->key[s] = -1;
@@ -534,6 +630,12 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   const bool raw_fallback = maxcol * span <= kRawWindow;
   const bool raw_only = maxcol * span <= a.raw_window;
   const int batch = 255 / maxcol > 0 ? 255 / maxcol : 1;
+  // a wave whose slot-less lanes want more than `gs` different subtrees counts
+  // them raw (one pass over the window per lane) rather than building each
+  // one's column vectors (about (64 + 2r) / 64 window columns per lane each)
+  const int gs = (9 * span) / ((12 * (64 + 2 * r)) / 64 + 6) > 1
+                     ? (9 * span) / ((12 * (64 + 2 * r)) / 64 + 6)
+                     : 1;
   const int maxrounds = ADAPT ? (3 * bits) / kTierLevels + 1 : (stop + kTierLevels - 1) / kTierLevels;
   int gr = 0;
 
@@ -579,13 +681,28 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           direct_counts(W, slots, cp16, slot, lx, span, batch);
         }
       }
-      // Pixels whose subtree no slot holds: small windows count their raw
-      // values; otherwise the wave builds each such subtree once in scratch.
-      if (raw_fallback) {
-        if (act && slot < 0) raw_counts<T, ADAPT, D3>(W, src, a, ts, topo, x, y, z, node, lo, hi,
-                                                      depth);
+      // Pixels whose subtree no slot holds: small windows, and waves whose
+      // lanes want many different subtrees, count their raw values; otherwise
+      // the wave builds each such subtree once in scratch.
+      const uint64_t nos = ballot(act && slot < 0);
+      bool use_raw = raw_fallback;
+      if (nos && !use_raw && !ADAPT) {
+        int g = 0;
+        for (uint64_t t = nos; t && g <= gs; ++g) {
+          const int leader = __builtin_ctzll(t);
+          t &= ~ballot(lo == readlane(lo, leader) && depth == readlane(depth, leader));
+        }
+        use_raw = g > gs;
+      }
+      if (nos && use_raw) {
+        if constexpr (ADAPT) {
+          if (act && slot < 0) raw_counts<T, ADAPT, D3>(W, src, a, ts, topo, x, y, z, node, lo, hi,
+                                                        depth);
+        } else {
+          raw_wave<T, D3>(W, act && slot < 0, lo, depth, scr, src, a, x0 + wv * 64, y, z, lane);
+        }
       } else
-      for (uint64_t fb = ballot(act && slot < 0); fb;) {
+      for (uint64_t fb = nos; fb;) {
         const int leader = __builtin_ctzll(fb);
         const int klo = readlane(lo, leader), khi = readlane(hi, leader);
         const int kdep = readlane(depth, leader), knode = readlane(node, leader);
@@ -654,17 +771,28 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
       if (tid == 0) ts->miss_n[(gr + 1) % 3] = 0;
       const uint64_t ex = ballot(exited);
       if (lane == 0) ts->flag[b][wv] = ex != 0;
+      // every exited lane looks its subtree up itself
       int newslot = -1;
-      for (uint64_t t = ex; t;) {
+      if (exited) {
+        newslot = ADAPT ? ht_find(ts->ht, key) : (ts->smap[key] == kNone ? -1 : (int)ts->smap[key]);
+        if (newslot >= 0) ts->stamp[newslot] = (int)y;  // the same value from every lane using it
+      }
+      // subtrees nobody holds are offered slots, at most kMissGroups per wave;
+      // when the wave wants more different subtrees than that (medians that
+      // change fast along the row), only those a group of lanes shares - the
+      // others would churn the slots - and the lanes left over are counted by
+      // the wave itself
+      uint64_t t = ballot(exited && newslot < 0);
+      int gm = 0;
+      for (uint64_t u = t; u && gm <= kMissGroups; ++gm)
+        u &= ~ballot(key == readlane(key, __builtin_ctzll(u)));
+      const int min_lanes = gm <= kMissGroups ? 1 : kSlotLanes;
+      for (int g = 0; t && g < kMissGroups; ++g) {
         const int leader = __builtin_ctzll(t);
         const int k = readlane(key, leader);
         const uint64_t m = ballot(key == k) & t;
         t &= ~m;
-        const int hs = ADAPT ? ht_find(ts->ht, k) : (ts->smap[k] == kNone ? -1 : ts->smap[k]);
-        if (hs >= 0) {
-          if (lane == leader) ts->stamp[hs] = (int)y;
-          if ((m >> lane) & 1) newslot = hs;
-        } else {
+        if (__builtin_popcountll(m) >= min_lanes) {
           if (lane == leader) {
             const int i = atomicAdd(&ts->miss_n[b], 1);
             if (i < kMissCap) {
@@ -684,7 +812,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
       ++gr;
       if (!any) break;
       if (nmiss > 0) {
-        if (tid == 0) assign_slots<ADAPT>(ts, nmiss, (int)y, a.nslots, stopo, topo);
+        if (tid == 0) assign_slots<ADAPT>(ts, nmiss, (int)y, a.nslots, stopo, topo, root);
         __syncthreads();
         const int nreb = ts->reb_n;
         if (nreb > 0) {
@@ -693,7 +821,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           for (int lc = tid; lc < ncols; lc += kBlock) {
             const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
             for (int i = 0; i < nreb; ++i) {
-              const int rs = ts->reb[i][0], rkey = ts->reb[i][1], rlo = ts->reb[i][2];
+              const int rs = ts->reb[i][0], rlo = ts->reb[i][2];
               const int rdep = ts->reb[i][3];
               const int rhi = ts->hi[rs];
               const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
@@ -868,8 +996,9 @@ hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32
   return hipGetLastError();
 }
 
-size_t tiered_meta_bytes(int r) {
-  return align16_host(sizeof(TierState)) + (size_t)kWaves * (64 + 2 * r + 1) * 16;
+size_t tiered_meta_bytes(int r, int bytes) {
+  const size_t st = bytes == 1 ? sizeof(TierState<uint8_t>) : sizeof(TierState<uint16_t>);
+  return align16_host(st) + (size_t)kWaves * wave_scratch_bytes(r);
 }
 
 size_t tiered_topo_bytes(int nslots) { return (size_t)nslots * 16 * sizeof(TopoNode); }

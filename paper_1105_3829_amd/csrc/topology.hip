@@ -5,7 +5,9 @@
 // removals (distributed like the input, i.e. its global histogram) and from
 // order-statistic descents (distributed like the output, estimated here by the
 // global histogram of the running box mean over the same window - the O(1)
-// first approximation the paper names).  The two histograms are mixed 1:1 and
+// first approximation the paper names - or, for a frame of a sequence, by the
+// global histogram of a caller-supplied estimate such as the previous frame's
+// median, the paper's suggestion for video).  The two histograms are mixed 1:1 and
 // every node is split where the mixed weight of its interval is halved
 // (ties to the smaller split).  Where the mixed weight of an interval is zero
 // the interval is halved by width, as in the uniform tree.
@@ -235,6 +237,19 @@ __global__ __launch_bounds__(kTB) void k_topo_level(int level, int bits, const u
 
 }  // namespace
 
+// Mixed-weight prefix sums, then the table one tree level per launch.
+static hipError_t build_levels(const Ws& w, int bits, TopoNode* topo, hipStream_t stream) {
+  const size_t nb = (size_t)1 << bits;
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, stream, w.hist_src, w.hist_mean, w.prefix,
+                     (int)nb);
+  hipLaunchKernelGGL(k_topo_init, dim3(1), dim3(64), 0, stream, w.front[0], w.ctrl, bits);
+  const int lgrid = (int)std::max<size_t>(1, (nb / 2 + kTB - 1) / kTB);
+  for (int level = 0; level < 3 * bits; ++level)
+    hipLaunchKernelGGL(k_topo_level, dim3(lgrid), dim3(kTB), 0, stream, level, bits, w.prefix,
+                       w.front[level & 1], w.front[(level + 1) & 1], w.ctrl, topo);
+  return hipGetLastError();
+}
+
 size_t topology_workspace_bytes(int bits, int64_t pixels) {
   const size_t nb = (size_t)1 << bits;
   return al(nb * 4) * 2 + al((nb + 1) * 8) + 2 * al(nb / 2 * sizeof(int4)) + al(16) +
@@ -242,7 +257,7 @@ size_t topology_workspace_bytes(int bits, int64_t pixels) {
 }
 
 hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* wsp, TopoNode* topo,
-                           hipStream_t stream) {
+                           hipStream_t stream, const void* est, int64_t est_rs) {
   const int bits = 8 * bytes;
   const int64_t pixels = a.w * a.h * a.d;
   Ws w = carve(wsp, bits, pixels);
@@ -260,6 +275,19 @@ hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* wsp, 
     (void)hipFuncSetAttribute((const void*)k_box<uint32_t, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)hlds);
     hipLaunchKernelGGL(k_hist<uint16_t>, dim3(hgrid), dim3(kTB), hlds, stream, a, w.hist_src);
+  }
+
+  if (est) {
+    // the estimate's own histogram stands in for the running mean's
+    MedianArgs e = a;
+    e.src = est;
+    e.srs = est_rs;
+    e.sss = est_rs * a.h;
+    if (bytes == 1)
+      hipLaunchKernelGGL(k_hist<uint8_t>, dim3(hgrid), dim3(kTB), hlds, stream, e, w.hist_mean);
+    else
+      hipLaunchKernelGGL(k_hist<uint16_t>, dim3(hgrid), dim3(kTB), hlds, stream, e, w.hist_mean);
+    return build_levels(w, bits, topo, stream);
   }
 
   // running box mean over the same window: separable clamp-to-edge sums
@@ -293,14 +321,7 @@ hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* wsp, 
                        (const uint32_t*)w.box[0], (int64_t)1, a.w, a.w * a.h, 1, a.w, a.h, a.d,
                        a.r, seg, nullptr, w.hist_mean, nwin, (int)nb);
   }
-  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, stream, w.hist_src, w.hist_mean, w.prefix,
-                     (int)nb);
-  hipLaunchKernelGGL(k_topo_init, dim3(1), dim3(64), 0, stream, w.front[0], w.ctrl, bits);
-  const int lgrid = (int)std::max<size_t>(1, (nb / 2 + kTB - 1) / kTB);
-  for (int level = 0; level < 3 * bits; ++level)
-    hipLaunchKernelGGL(k_topo_level, dim3(lgrid), dim3(kTB), 0, stream, level, bits, w.prefix,
-                       w.front[level & 1], w.front[(level + 1) & 1], w.ctrl, topo);
-  return hipGetLastError();
+  return build_levels(w, bits, topo, stream);
 }
 
 }  // namespace hrrm

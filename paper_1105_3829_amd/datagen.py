@@ -68,6 +68,28 @@ def xray_u16(h: int, w: int, seed: int = 1, ramp: bool = True) -> np.ndarray:
     return np.clip(np.rint(v), 0, 4095).astype(np.uint16)
 
 
+def xray_frames_u16(n: int, h: int, w: int, seed: int = 5) -> np.ndarray:
+    """A seeded sequence of n X-ray-like frames (n, h, w): fresh mixture noise
+    per frame (as xray_u16), the ramp, a global brightness drift of +30 grey
+    levels per frame and a disc-shaped absorber (-600) of radius min(h, w)/8
+    moving from 20 % to 80 % of the width along the middle row."""
+    g = rng(seed)
+    xs = np.arange(w, dtype=np.float32)
+    ys = np.arange(h, dtype=np.float32)
+    ramp = 150.0 * (xs[None, :] / np.float32(max(w - 1, 1)) +
+                    ys[:, None] / np.float32(max(h - 1, 1))) - 150.0
+    out = np.empty((n, h, w), dtype=np.uint16)
+    rad2 = (min(h, w) / 8.0) ** 2
+    for t in range(n):
+        v = _mixture(g, (h, w)) + ramp + np.float32(30.0 * t)
+        cx = (0.2 + 0.6 * t / max(n - 1, 1)) * (w - 1)
+        cy = 0.5 * (h - 1)
+        disc = (xs[None, :] - cx) ** 2 + (ys[:, None] - cy) ** 2 < rad2
+        v[disc] -= 600.0
+        out[t] = np.clip(np.rint(v), 0, 4095).astype(np.uint16)
+    return out
+
+
 def lowkey_u8(h: int, w: int, seed: int = 2) -> np.ndarray:
     g = rng(seed)
     e = np.floor(g.exponential(20.0, size=(h, w)).astype(np.float32))

@@ -240,6 +240,41 @@ def test_full_update_rank_3d_and_errors(hrrm):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("r", [2, 9])
+def test_video_sequence_u16(hrrm, r):
+    # frame t's topology comes from frame t-1's median output (left on the
+    # device); frame 0 falls back to the running mean
+    import torch
+    frames = datagen.xray_frames_u16(4, 110, 300, seed=140 + r)
+    prev = None
+    for t in range(frames.shape[0]):
+        announce("video", "r=%d" % r, "frame", t)
+        cur = hrrm.median2d_video(to_dev(frames[t]), r, estimate=prev)
+        want = oracle.median2d(frames[t], r)
+        assert np.array_equal(to_host(cur), want), first_mismatch(to_host(cur), want)
+        prev = cur
+    # output written over the estimate buffer itself
+    est = to_dev(oracle.median2d(frames[2], r))
+    got = hrrm.median2d_video(to_dev(frames[3]), r, estimate=est, out=est)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(got), oracle.median2d(frames[3], r))
+
+
+def test_video_u8_and_degenerate_estimates(hrrm):
+    frames = [datagen.lowkey_u8(90, 280, seed=150 + t) for t in range(3)]
+    prev = None
+    for t, f in enumerate(frames):
+        cur = hrrm.median2d_video(to_dev(f), 5, estimate=prev)
+        assert np.array_equal(to_host(cur), oracle.median2d(f, 5)), t
+        prev = cur
+    # estimates unrelated to the frame (constant, all-maximum) change speed, never results
+    img = datagen.xray_u16(100, 270, seed=151)
+    for fill in (0, 4095, 65535):
+        est = to_dev(np.full(img.shape, fill, np.uint16))
+        got = to_host(hrrm.median2d_video(to_dev(img), 6, estimate=est))
+        assert np.array_equal(got, oracle.median2d(img, 6)), fill
+
+
 @pytest.mark.parametrize("bits_free", [0, 1, 3, 5, 9])
 def test_u16_common_prefix(hrrm, bits_free):
     # 16-bit values confined to an aligned or unaligned band: the tile's common
