@@ -275,6 +275,28 @@ def test_video_u8_and_degenerate_estimates(hrrm):
         assert np.array_equal(got, oracle.median2d(img, 6)), fill
 
 
+@pytest.mark.parametrize("r", [3, 12, 40])
+def test_u16_diagonal_sine(hrrm, r):
+    # the paper's worst case: medians change fast along every row, so a wave's
+    # pixels want many different deep subtrees (raw counting and wave-local
+    # subtree builds instead of slots)
+    img = datagen.diagonal_sine(96, 700, period=100.0, bits=16)
+    _check2d(hrrm, img, r)
+    _check2d(hrrm, datagen.diagonal_sine(80, 300, period=25.0, bits=16), r)
+
+
+@pytest.mark.parametrize("r", [4, 15, 50])
+def test_u16_sharp_edge(hrrm, r):
+    # a disc 600 grey levels darker than the X-ray-like background: along rows
+    # that cross its rim the medians sweep through many deep subtrees
+    img = datagen.xray_u16(200, 600, seed=160 + r).astype(np.int32)
+    yy, xx = np.mgrid[0:200, 0:600]
+    img[(xx - 300) ** 2 + (yy - 100) ** 2 < 80 ** 2] -= 600
+    img = np.clip(img, 0, 4095).astype(np.uint16)
+    _check2d(hrrm, img, r)
+    _check2d(hrrm, img, r, "adaptive")
+
+
 @pytest.mark.parametrize("bits_free", [0, 1, 3, 5, 9])
 def test_u16_common_prefix(hrrm, bits_free):
     # 16-bit values confined to an aligned or unaligned band: the tile's common
