@@ -531,7 +531,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                                 align16(sizeof(TS)) + (size_t)kWaves * wave_scratch_bytes(r));
   const int root = ADAPT ? topo[(1 << bits) - 1].split : 1;
   const int maxv = (1 << bits) - 1;
-  const int ntiers = (bits + kTierLevels - 1) / kTierLevels;
+  constexpr int ntiers = (bits + kTierLevels - 1) / kTierLevels;
 
   // ---- set-up: tables, empty slots
   if (tid < 16) {
@@ -857,7 +857,51 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
     // ---- next window: every column drops row y-r and takes row y+r+1
     if (y + 1 < ye) {
       const int64_t yo = clampi(y - r, a.h - 1), yi = clampi(y + r + 1, a.h - 1);
-      if (yo != yi) {
+      if (!ADAPT && !D3 && yo != yi) {
+        // uniform 2-D: the thread owns columns tid and tid + 256 (if any); per
+        // tier the slots and masks of both columns' leaving and entering values
+        // are looked up together, and a column whose two values fall in the
+        // same held subtree is updated once (removal applied first)
+        const bool two = tid + kBlock < ncols;
+#pragma unroll
+        for (int t = 0; t < ntiers; ++t) {
+          const int rel = t * kTierLevels, dep = pl + rel;
+          if (dep >= stop) break;
+          const uint4 lim = level_mask(stop - dep < kTierLevels ? stop - dep : kTierLevels);
+          const int mk = (1 << rel) - 1;
+          int so[2] = {0, 0}, si[2] = {0, 0};
+          uint4 mo[2], mi[2];
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (t > 0) {
+              so[k] = ts->smap[ukey(rel, (pre_o[k] >> (bits - dep)) & mk)];
+              si[k] = ts->smap[ukey(rel, (pre_i[k] >> (bits - dep)) & mk)];
+            }
+            mo[k] = and4(ts->lut[nib(pre_o[k], dep, bits)], lim);
+            mi[k] = and4(ts->lut[nib(pre_i[k], dep, bits)], lim);
+          }
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            if (k == 1 && !two) break;
+            const int lc = tid + k * kBlock;
+            if (so[k] == si[k]) {
+              if (so[k] != (int)kNone) {
+                uint4& cv = vec(slots, cp16, so[k], lc);
+                cv = add4(sub4(cv, mo[k]), mi[k]);
+              }
+            } else {
+              if (so[k] != (int)kNone) {
+                uint4& cv = vec(slots, cp16, so[k], lc);
+                cv = sub4(cv, mo[k]);
+              }
+              if (si[k] != (int)kNone) {
+                uint4& cv = vec(slots, cp16, si[k], lc);
+                cv = add4(cv, mi[k]);
+              }
+            }
+          }
+        }
+      } else if (yo != yi) {
         for (int lc = tid; lc < ncols; lc += kBlock) {
           const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
           for (int pass = 0; pass < 2; ++pass) {  // removals first, then insertions
