@@ -857,11 +857,54 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
     // ---- next window: every column drops row y-r and takes row y+r+1
     if (y + 1 < ye) {
       const int64_t yo = clampi(y - r, a.h - 1), yi = clampi(y + r + 1, a.h - 1);
-      if (!ADAPT && !D3 && yo != yi) {
+      // one column of the uniform tree: value vo leaves, vi enters; a subtree
+      // holding both is updated once, removal first (no byte ever exceeds the
+      // column's value count)
+      auto pair_update = [&](int lc, int so, int si, uint4 mo, uint4 mi) {
+        if (so == si) {
+          if (so != (int)kNone) {
+            uint4& cv = vec(slots, cp16, so, lc);
+            cv = add4(sub4(cv, mo), mi);
+          }
+        } else {
+          if (so != (int)kNone) {
+            uint4& cv = vec(slots, cp16, so, lc);
+            cv = sub4(cv, mo);
+          }
+          if (si != (int)kNone) {
+            uint4& cv = vec(slots, cp16, si, lc);
+            cv = add4(cv, mi);
+          }
+        }
+      };
+      if (!ADAPT && D3 && yo != yi) {
+        // uniform 3-D: per column and slice, the leaving and entering values
+        for (int lc = tid; lc < ncols; lc += kBlock) {
+          const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
+          for (int dz = -zr; dz <= zr; ++dz) {
+            const int64_t zz = clampi(z + dz, a.d - 1);
+            const int vo = src[zz * a.sss + yo * a.srs + cx];
+            const int vi = src[zz * a.sss + yi * a.srs + cx];
+#pragma unroll
+            for (int t = 0; t < ntiers; ++t) {
+              const int rel = t * kTierLevels, dep = pl + rel;
+              if (dep >= stop) break;
+              const uint4 lim = level_mask(stop - dep < kTierLevels ? stop - dep : kTierLevels);
+              int so = 0, si = 0;
+              if (t > 0) {
+                const int mk = (1 << rel) - 1;
+                so = ts->smap[ukey(rel, (vo >> (bits - dep)) & mk)];
+                si = ts->smap[ukey(rel, (vi >> (bits - dep)) & mk)];
+              }
+              pair_update(lc, so, si, and4(ts->lut[nib(vo, dep, bits)], lim),
+                          and4(ts->lut[nib(vi, dep, bits)], lim));
+            }
+          }
+        }
+      } else if (!ADAPT && !D3 && yo != yi) {
         // uniform 2-D: the thread owns columns tid and tid + 256 (if any); per
         // tier the slots and masks of both columns' leaving and entering values
-        // are looked up together, and a column whose two values fall in the
-        // same held subtree is updated once (removal applied first)
+        // are looked up together
         const bool two = tid + kBlock < ncols;
 #pragma unroll
         for (int t = 0; t < ntiers; ++t) {
@@ -880,26 +923,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
             mo[k] = and4(ts->lut[nib(pre_o[k], dep, bits)], lim);
             mi[k] = and4(ts->lut[nib(pre_i[k], dep, bits)], lim);
           }
-#pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            if (k == 1 && !two) break;
-            const int lc = tid + k * kBlock;
-            if (so[k] == si[k]) {
-              if (so[k] != (int)kNone) {
-                uint4& cv = vec(slots, cp16, so[k], lc);
-                cv = add4(sub4(cv, mo[k]), mi[k]);
-              }
-            } else {
-              if (so[k] != (int)kNone) {
-                uint4& cv = vec(slots, cp16, so[k], lc);
-                cv = sub4(cv, mo[k]);
-              }
-              if (si[k] != (int)kNone) {
-                uint4& cv = vec(slots, cp16, si[k], lc);
-                cv = add4(cv, mi[k]);
-              }
-            }
-          }
+          pair_update(tid, so[0], si[0], mo[0], mi[0]);
+          if (two) pair_update(tid + kBlock, so[1], si[1], mo[1], mi[1]);
         }
       } else if (yo != yi) {
         for (int lc = tid; lc < ncols; lc += kBlock) {
