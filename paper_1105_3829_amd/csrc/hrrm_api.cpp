@@ -46,7 +46,6 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
                         int64_t d, bool fill_gpu) {
   TileConfig t{};
   t.tiered_u8 = 1;  // the radix-16 tiered kernel is also the faster one for 8-bit data
-  const int span = 2 * r + 1;
   t.min_group = 2;
   t.nslots = 0;
   t.lds_budget = 80 * 1024;  // two workgroups per CU
@@ -68,10 +67,9 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     else
       rows = r <= 2 ? 32 : 128;
   } else {
-    // per-lane sums cost about 6.5 instructions per column, a cooperative
-    // prefix sum about 170: take prefix sums while they are cheaper
-    t.max_groups = std::max(1, (int)((6.5 * span + 40) / 170));
-    rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
+    // measured on a 512 x 512 x 256 16-bit volume, r = 1..7
+    t.max_groups = r <= 3 ? 0 : 2;
+    rows = r <= 1 ? 32 : r <= 3 ? 64 : 256;
   }
   // an image filtered on its own keeps at least ~1024 tiles (four per
   // workgroup slot of the GPU) when it allows it; in a batch the other images
