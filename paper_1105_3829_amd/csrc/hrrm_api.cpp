@@ -40,6 +40,33 @@ void clear_error() { g_err.clear(); }
 
 const char* last_error() { return g_err.c_str(); }
 
+// ---- kernel attributes ---------------------------------------------------
+
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes) {
+  struct Entry {
+    const void* kernel;
+    int device;
+    size_t bytes;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> set;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& s : set) {
+    if (s.kernel == kernel && s.device == dev) {
+      if (s.bytes >= bytes) return hipSuccess;
+      e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e == hipSuccess) s.bytes = bytes;
+      return e;
+    }
+  }
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) set.push_back({kernel, dev, bytes});
+  return e;
+}
+
 // ---- tile table ------------------------------------------------------------
 
 TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h,

@@ -79,6 +79,12 @@ struct TileConfig {
 hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive, bool tiered,
                          bool full, hipStream_t stream);
 
+// Raise `kernel`'s dynamic-LDS limit on the current device to at least
+// `bytes`.  The attribute is set only when a launch needs more than every
+// earlier one of that kernel on that device, so steady-state launches (and
+// launches under stream capture) make no attribute call.
+hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
+
 // LDS bytes a launch with these parameters needs.
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);
 

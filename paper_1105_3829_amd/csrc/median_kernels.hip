@@ -308,8 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_median_dense(MedianArgs a) {
 template <bool ADAPT, bool D3, bool FULL>
 hipError_t launch_dense(const MedianArgs& a, size_t lds, hipStream_t stream) {
   auto kern = k_median_dense<uint8_t, ADAPT, D3, FULL>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;
   hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(kBlock), lds, stream, a);

@@ -1040,8 +1040,7 @@ __global__ void k_zero_counter(uint32_t* counter) {
 template <typename T, bool ADAPT, bool D3>
 hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
   auto kern = k_median_tiered<T, ADAPT, D3>;
-  hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;
   hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(kBlock), lds, stream, a);
@@ -1053,8 +1052,7 @@ size_t align16_host(size_t b) { return (b + 15) & ~(size_t)15; }
 }  // namespace
 
 hipError_t launch_batched_prepare(size_t lds) {
-  return hipFuncSetAttribute((const void*)k_median_batched,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return ensure_dynamic_lds((const void*)k_median_batched, lds);
 }
 
 hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32_t* d_counter,

@@ -270,10 +270,9 @@ hipError_t launch_topology(const MedianArgs& a, int bytes, int dims, void* wsp, 
   if (bytes == 1) {
     hipLaunchKernelGGL(k_hist<uint8_t>, dim3(hgrid), dim3(kTB), hlds, stream, a, w.hist_src);
   } else {
-    (void)hipFuncSetAttribute((const void*)k_hist<uint16_t>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)hlds);
-    (void)hipFuncSetAttribute((const void*)k_box<uint32_t, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)hlds);
+    hipError_t e = ensure_dynamic_lds((const void*)k_hist<uint16_t>, hlds);
+    if (e == hipSuccess) e = ensure_dynamic_lds((const void*)k_box<uint32_t, true>, hlds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hist<uint16_t>, dim3(hgrid), dim3(kTB), hlds, stream, a, w.hist_src);
   }
 
