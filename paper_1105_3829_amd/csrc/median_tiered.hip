@@ -755,6 +755,9 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           }
         }
       }
+      // Uniform trees: after the tier that reaches the stop depth every pixel
+      // is done, in every wave, so no transition (and no barrier) follows.
+      if (!ADAPT && pl + kTierLevels * (round + 1) >= stop) break;
       // Tier transition: pixels entering a deeper subtree look up its slot;
       // subtrees no slot holds are queued as misses for thread 0.
       const bool exited = !done;
