@@ -175,6 +175,9 @@ def main():
                     help="also run a plain device copy of one image (counter calibration)")
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the replayed serving trace (0 = skip serving)")
+    ap.add_argument("--saturation-rate", type=float, default=4000.0,
+                    help="request rate of the overload trace (0 = skip it)")
+    ap.add_argument("--saturation-seconds", type=float, default=2.5)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -281,6 +284,18 @@ def main():
             "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"],
             "throughput_gain": round(b["completed_mpix_s_in_window"] /
                                      max(p["completed_mpix_s_in_window"], 1e-9), 3)}
+        if args.saturation_rate > 0:
+            # the same trace recipe at a rate neither mode can sustain: the
+            # completed throughput inside the window is each mode's capacity
+            sb = serving(args.saturation_seconds, rate=args.saturation_rate, per_image=False,
+                         pools=pools)
+            sp = serving(args.saturation_seconds, rate=args.saturation_rate, per_image=True,
+                         pools=pools)
+            res["serving"]["saturated"] = {
+                "rate_hz": args.saturation_rate, "seconds": args.saturation_seconds,
+                "batched": sb, "per_image": sp,
+                "throughput_gain": round(sb["completed_mpix_s_in_window"] /
+                                         max(sp["completed_mpix_s_in_window"], 1e-9), 3)}
     if not args.no_cpu_baseline:
         print("cpu baseline: timing the oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(img, args.r)
