@@ -78,7 +78,10 @@ const char* hrrm_version(void);
 /* Create a context bound to HIP device `device`.  The context owns device
  * workspaces (adaptive-topology histograms and tables) and the tile
  * configuration table; it is not thread-safe (one context per host thread, or
- * external locking).  *out receives the handle. */
+ * external locking).  Adaptive calls (HRRM_ADAPTIVE, hrrm_median2d_video) of
+ * one context share its topology workspace: enqueue them on one stream, or
+ * order them; other calls of a context may run on any streams concurrently.
+ * *out receives the handle. */
 int hrrm_ctx_create(int device, hrrm_ctx* out);
 
 /* Destroy a context and free its workspaces.  The caller must make sure no
@@ -86,8 +89,9 @@ int hrrm_ctx_create(int device, hrrm_ctx* out);
 int hrrm_ctx_destroy(hrrm_ctx ctx);
 
 /* Pre-size the workspaces so later calls up to these sizes allocate nothing
- * (required before capturing calls into a HIP graph).  max_pixels counts
- * pixels (2-D) or voxels (3-D). */
+ * (required before capturing adaptive calls into a HIP graph: a call that
+ * would have to grow a workspace while its stream is being captured fails
+ * with ENOMEM).  max_pixels counts pixels (2-D) or voxels (3-D). */
 int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t max_r,
                      hrrm_variant variant);
 

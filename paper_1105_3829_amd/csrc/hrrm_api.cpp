@@ -235,7 +235,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
   if (adaptive) {
-    int rc = ctx->ensure_topology(bytes, w * h * a.d);
+    int rc = ctx->ensure_topology(bytes, w * h * a.d, stream);
     if (rc != HRRM_OK) return rc;
     a.topo = (const TopoNode*)ctx->topo;
     e = launch_topology(a, bytes, dims, ctx->topo_ws, (TopoNode*)ctx->topo, stream, est, est_rs);
@@ -248,12 +248,19 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
 
 // ---- context -----------------------------------------------------------------
 
-int Context::ensure_topology(int bytes, int64_t pixels) {
+int Context::ensure_topology(int bytes, int64_t pixels, hipStream_t stream) {
   const int bits = 8 * bytes;
   const size_t need_ws = topology_workspace_bytes(bits, pixels);
   const size_t need_topo = sizeof(TopoNode) << bits;  // nodes + root entry
+  if (need_ws <= topo_ws_bytes && need_topo <= topo_bytes) return HRRM_OK;
+  // growing allocates (and hipFree waits for the device): not allowed while
+  // the stream is being captured into a graph
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (stream && hipStreamIsCapturing(stream, &cs) == hipSuccess &&
+      cs != hipStreamCaptureStatusNone)
+    return fail(HRRM_ENOMEM, "adaptive workspace too small under stream capture "
+                             "(call hrrm_ctx_reserve before capturing)");
   if (need_ws > topo_ws_bytes) {
-    if (capture_locked) return fail(HRRM_ENOMEM, "workspace too small (reserve before capture)");
     if (topo_ws) (void)hipFree(topo_ws);
     topo_ws = nullptr;
     topo_ws_bytes = 0;
@@ -262,7 +269,6 @@ int Context::ensure_topology(int bytes, int64_t pixels) {
     topo_ws_bytes = need_ws;
   }
   if (need_topo > topo_bytes) {
-    if (capture_locked) return fail(HRRM_ENOMEM, "workspace too small (reserve before capture)");
     if (topo) (void)hipFree(topo);
     topo = nullptr;
     topo_bytes = 0;
@@ -326,7 +332,8 @@ int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t
   if (max_pixels < 0 || max_r < 0) return fail(HRRM_EINVAL, "negative size");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
-  if (variant == HRRM_ADAPTIVE) return c->ensure_topology(dtype == HRRM_U8 ? 1 : 2, max_pixels);
+  if (variant == HRRM_ADAPTIVE)
+    return c->ensure_topology(dtype == HRRM_U8 ? 1 : 2, max_pixels, nullptr);
   return HRRM_OK;
 }
 

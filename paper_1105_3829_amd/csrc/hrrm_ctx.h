@@ -34,7 +34,6 @@ struct Context {
   size_t topo_ws_bytes = 0;
   void* topo = nullptr;  // TopoNode[2^bits], last entry holds the root index
   size_t topo_bytes = 0;
-  bool capture_locked = false;
   std::vector<TunedEntry> tuned;
 
   // batched launches (persistent kernel), one entry per stream used
@@ -43,7 +42,10 @@ struct Context {
   // fill_gpu: the image runs on its own, so small images get shorter segments
   TileConfig tile_for(int bytes, int dims, int r, bool adaptive, int64_t w, int64_t h, int64_t d,
                       bool fill_gpu = true) const;
-  int ensure_topology(int bytes, int64_t pixels);
+  // grow the adaptive workspace to `pixels` (refused while `stream` is being
+  // captured); a grown workspace replaces the old one after hipFree, which
+  // waits for the device
+  int ensure_topology(int bytes, int64_t pixels, hipStream_t stream);
   void release_batch();
   BatchStream* batch_for(hipStream_t s);
   ~Context();
