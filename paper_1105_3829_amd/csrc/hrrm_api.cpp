@@ -83,25 +83,32 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   const int64_t strips = (w + kBlock - 1) / kBlock;
   int64_t rows;
   if (dims == 2) {
-    // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..100):
+    // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..127):
     // cooperative prefix sums pay off for up to 1, 2 or 4 distinct subtrees
-    // per wave as the window widens; short segments suit wide 16-bit windows,
-    // whose deep tiers are expensive enough that more, smaller tiles balance
-    // the CUs better than the repeated start-up (2r+1 rows per column) costs.
+    // per wave as the window widens.  16-bit windows up to r = 31 run two
+    // workgroups per CU with short segments; wider ones need more slots than
+    // 80 KB holds (slot churn grows with the segment) and run one workgroup
+    // per CU with the whole 160 KB and tall segments.
     t.max_groups = r <= 7 ? 0 : r <= 11 ? 1 : r <= 31 ? 2 : 4;
-    if (bytes == 2)
-      rows = r <= 3 ? 32 : r <= 5 ? 64 : r <= 31 ? 48 : r <= 63 ? 24 : 8;
-    else
-      rows = r <= 2 ? 32 : 128;
+    if (bytes == 2) {
+      if (r >= 36) {
+        t.lds_budget = kLdsLimit;
+        rows = 256;
+      } else {
+        rows = r <= 3 ? 32 : r <= 5 ? 64 : 48;
+      }
+    } else {
+      rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
+    }
   } else {
     // measured on a 512 x 512 x 256 16-bit volume, r = 1..7
     t.max_groups = r <= 3 ? 0 : 2;
     rows = r <= 1 ? 32 : r <= 3 ? 64 : 256;
   }
-  // an image filtered on its own keeps at least ~1024 tiles (four per
-  // workgroup slot of the GPU) when it allows it; in a batch the other images
-  // fill the GPU
-  const int64_t want = 1024;
+  // an image filtered on its own keeps at least two tiles per workgroup slot
+  // of the GPU (256 CUs, 1 or 2 workgroups each) when it allows it; in a batch
+  // the other images fill the GPU
+  const int64_t want = t.lds_budget > kLdsLimit / 2 ? 512 : 1024;
   const int64_t fill = (strips * h * d + want - 1) / want;
   if (fill_gpu && strips * ((h + rows - 1) / rows) * d < want)
     rows = std::max<int64_t>(8, std::min(rows, fill));
