@@ -85,17 +85,20 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   if (dims == 2) {
     // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..127):
     // cooperative prefix sums pay off for up to 1, 2 or 4 distinct subtrees
-    // per wave as the window widens.  16-bit windows up to r = 31 run two
-    // workgroups per CU with short segments; wider ones need more slots than
-    // 80 KB holds (slot churn grows with the segment) and run one workgroup
-    // per CU with the whole 160 KB and tall segments.
+    // per wave as the window widens.  16-bit windows run two workgroups per
+    // CU with short segments up to r = 63; from r = 64 smooth images need
+    // more slots than 80 KB holds (the churn grows with the segment) and run
+    // one workgroup per CU with the whole 160 KB and tall segments (4x faster
+    // at r = 100).  Images whose medians change fast along rows (edges) would
+    // rather keep two workgroups per CU there (1.6x); the autotuner picks
+    // per workload.
     t.max_groups = r <= 7 ? 0 : r <= 11 ? 1 : r <= 31 ? 2 : 4;
     if (bytes == 2) {
-      if (r >= 36) {
+      if (r >= 64) {
         t.lds_budget = kLdsLimit;
-        rows = 256;
+        rows = 128;
       } else {
-        rows = r <= 3 ? 32 : r <= 5 ? 64 : 48;
+        rows = r <= 3 ? 32 : r <= 5 ? 64 : r <= 31 ? 48 : 24;
       }
     } else {
       rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
