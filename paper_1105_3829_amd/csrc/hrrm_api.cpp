@@ -103,10 +103,19 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     } else {
       rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
     }
-  } else {
-    // measured on a 512 x 512 x 256 16-bit volume, r = 1..7
+  } else if (!adaptive) {
+    // measured on a 512 x 512 x 256 16-bit volume, r = 1..7 (at r = 2 the
+    // medians of 125-value cubes spread over more deep subtrees than 80 KB
+    // of slots hold: the whole LDS pays there)
     t.max_groups = r <= 3 ? 0 : 2;
-    rows = r <= 1 ? 32 : r <= 3 ? 64 : 256;
+    rows = r <= 1 ? 32 : r == 2 ? 256 : r <= 3 ? 64 : 256;
+    if (r == 2 && bytes == 2) t.lds_budget = kLdsLimit;
+  } else {
+    // adaptive volumes: more distinct subtrees per row, so shorter segments
+    // (fewer rows walking the same slots) and per-lane sums past one group
+    const int span = 2 * r + 1;
+    t.max_groups = 1;
+    rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
   }
   // an image filtered on its own keeps at least two tiles per workgroup slot
   // of the GPU (256 CUs, 1 or 2 workgroups each) when it allows it; in a batch
@@ -117,7 +126,6 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     rows = std::max<int64_t>(8, std::min(rows, fill));
   rows = std::min<int64_t>(rows, 512);
   t.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(rows, h));
-  (void)adaptive;
   return t;
 }
 
