@@ -715,7 +715,29 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         wave_sync_lds();
       }
       // Descend (up to) the four levels of this tier.
-      if (act) {
+      if (!ADAPT && act) {
+        // uniform tree: every level halves the interval, so the levels taken
+        // right spell the next value bits; the lane's levels in this tier end
+        // at the stop depth
+        const int lv = stop - depth < kTierLevels ? stop - depth : kTierLevels;
+        int p = 1;
+#pragma unroll
+        for (int k = 0; k < kTierLevels; ++k) {
+          if (k < lv) {
+            const uint32_t wl = k == 0 ? (W[0] & 0xffffu) : wsel(W, p - 1);
+            const bool right = acc + wl <= K;
+            acc += right ? wl : 0u;
+            p = 2 * p + (right ? 1 : 0);
+          }
+        }
+        lo += (p - (1 << lv)) << (bits - depth - lv);
+        hi = lo + (1 << (bits - depth - lv)) - 1;
+        depth += lv;
+        if (depth >= stop) {
+          done = true;
+          res = lo;
+        }
+      } else if (act) {
         int p = 1;
 #pragma unroll
         for (int k = 0; k < kTierLevels; ++k) {
