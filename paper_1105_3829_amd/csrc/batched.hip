@@ -101,7 +101,9 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     // the batch runs two workgroups per CU; a tile tuned for the whole LDS of
     // a CU (wide 16-bit windows) gets short segments instead, as slots churn
     // more the more rows a segment walks
-    const int64_t seg = (size_t)t.lds_budget > kBatchLds ? (im.r <= 63 ? 24 : 8) : t.seg_rows;
+    // (and segments of at most 128 rows: many short images share the GPU)
+    const int64_t seg = (size_t)t.lds_budget > kBatchLds ? (im.r <= 63 ? 24 : 8)
+                                                          : std::min<int64_t>(t.seg_rows, 128);
     a.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(seg, im.height));
     a.strips = (int32_t)((im.width + kBlock - 1) / kBlock);
     a.segs = (int32_t)((im.height + a.seg_rows - 1) / a.seg_rows);
