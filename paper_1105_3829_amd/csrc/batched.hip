@@ -119,6 +119,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     a.min_group = std::max(1, t.min_group);
     a.max_groups = std::max(0, t.max_groups);
     a.raw_window = std::max(0, t.raw_window);
+    a.mfma = 2 * im.r + 1 <= 127;  // column counts as signed bytes
     tiles += (int64_t)a.strips * a.segs;
     if (tiles > 0x7fffffff) return fail(HRRM_EUNSUPPORTED, "batch has too many tiles");
     b.tile_end = tiles;

@@ -84,15 +84,19 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   int64_t rows;
   if (dims == 2) {
     // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..127):
-    // cooperative prefix sums pay off for up to 1, 2 or 4 distinct subtrees
-    // per wave as the window widens.  16-bit windows run two workgroups per
+    // counting a tier for all 64 pixels of a wave at once (matrix cores, or
+    // prefix sums past 127-value columns) pays off for more distinct subtrees
+    // per wave the wider the window; narrow windows sum per lane.  16-bit windows run two workgroups per
     // CU with short segments up to r = 63; from r = 64 smooth images need
     // more slots than 80 KB holds (the churn grows with the segment) and run
     // one workgroup per CU with the whole 160 KB and tall segments (4x faster
     // at r = 100).  Images whose medians change fast along rows (edges) would
     // rather keep two workgroups per CU there (1.6x); the autotuner picks
     // per workload.
-    t.max_groups = r <= 7 ? 0 : r <= 11 ? 1 : r <= 31 ? 2 : 4;
+    if (bytes == 2)
+      t.max_groups = r <= 7 ? 0 : r <= 15 ? 1 : r <= 31 ? 4 : 64;
+    else
+      t.max_groups = r <= 4 ? 0 : r <= 8 ? 1 : 64;
     if (bytes == 2) {
       if (r >= 64) {
         t.lds_budget = kLdsLimit;
@@ -227,6 +231,8 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   a.min_group = std::max(1, t.min_group);
   a.max_groups = std::max(0, t.max_groups);
   a.raw_window = std::max(0, t.raw_window);
+  // the matrix cores take column counts as signed bytes
+  a.mfma = (dims == 3 ? (2 * r + 1) * (2 * r + 1) : 2 * r + 1) <= 127;
   a.topo = nullptr;
 
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;

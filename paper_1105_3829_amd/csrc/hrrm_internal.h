@@ -49,7 +49,7 @@ struct MedianArgs {
   int32_t min_group;  // smallest lane group counted cooperatively
   int32_t max_groups; // cooperative groups per level before falling back to direct sums
   int32_t raw_window; // windows of at most this many values count a missing subtree raw
-  int32_t pad0;
+  int32_t mfma;       // 1: window counts on the matrix cores (column counts <= 127)
   const TopoNode* topo;  // adaptive topology (device), else null
 };
 

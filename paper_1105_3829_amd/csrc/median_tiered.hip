@@ -254,6 +254,89 @@ __device__ __forceinline__ void coop_counts(uint32_t (&W)[8], const uint8_t* slo
   }
 }
 
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+// Window counts as a matrix product on the matrix cores.  For the tier subtree
+// of one slot and the wave's 64 pixels, counts[node][pixel] =
+// sum_k col[k][node] * band[k][pixel], where k runs over the 64 + 2r columns
+// the wave's windows cover and band[k][pixel] = 1 when column k lies in the
+// pixel's window - the paper's window update (Sec. III) summed for all nodes
+// of the tier at once.  Column counts enter as signed bytes (at most 127).
+//
+// Operands of v_mfma_i32_16x16x64_i8: lane l holds A[i = l % 16][k = 16(l/16)
+// + b] and B[k = 16(l/16) + b][j = l % 16] for b = 0..15, and receives
+// D[4(l/16) + v][l % 16] for v = 0..3.  Here A = column counts (node x k),
+// read transposed from the column-major slot by ds_read_b64_tr_b8: lane t of a
+// 16-lane group names half t % 2 of column c0 + t / 2, and receives node t of
+// columns c0 .. c0 + 7.  B = band (k x pixel), built once per tile.
+struct Band {
+  v4i_t f[3][4];  // [64-column step][16-pixel tile]
+  int steps;
+};
+
+__device__ __forceinline__ void band_init(Band& bd, int span, int lane) {
+  const int g = lane >> 4, t = lane & 15;
+  bd.steps = (64 + span - 1 + 63) >> 6;
+#pragma unroll
+  for (int ks = 0; ks < 3; ++ks)
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      // bytes b with 0 <= k - p < span, k = 64ks + 16g + b, p = 16nt + t
+      const int d = 64 * ks + 16 * (g - nt) - t;
+      const int blo = -d < 0 ? 0 : (-d > 16 ? 16 : -d);
+      const int bhi = span - d < 0 ? 0 : (span - d > 16 ? 16 : span - d);
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t x = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x |= (4 * q + b >= blo && 4 * q + b < bhi) ? 1u << (8 * b) : 0u;
+        w[q] = x;
+      }
+      bd.f[ks][nt] = v4i_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+    }
+}
+
+// Counts of slot s for the pixels of `m` into the wave's staging area
+// (pixel p at p * 32 bytes, in the packed layout wsel reads).  All 64 lanes
+// must call it.
+__device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots, size_t cp16,
+                                           int cp, int s, uint64_t m, int wbase, int lane,
+                                           uint8_t* stage) {
+  const int g = lane >> 4, t = lane & 15;
+  const uint8_t* sb = slots + (size_t)s * cp16;
+  const int cb = wbase + 1;  // first window column of the wave's first pixel
+  v4i_t acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+  for (int ks = 0; ks < 3; ++ks) {
+    if (ks < bd.steps) {
+      v4i_t a;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int c = cb + 64 * ks + 16 * g + 8 * h + (t >> 1);
+        c = c < cp - 1 ? c : cp - 1;  // past the strip: band weight 0
+        const v2i_t rr = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
+            (v2i_t __attribute__((address_space(3)))*)(sb + (size_t)c * 16 + 8 * (t & 1)));
+        a[2 * h] = rr.x;
+        a[2 * h + 1] = rr.y;
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bd.f[ks][nt], acc[nt], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int p = 16 * nt + t;
+    if ((m >> p) & 1) {
+      const uint32_t w0 = (uint32_t)acc[nt][0] | ((uint32_t)acc[nt][2] << 16);
+      const uint32_t w1 = (uint32_t)acc[nt][1] | ((uint32_t)acc[nt][3] << 16);
+      *(uint2*)(stage + p * 32 + 8 * g) = make_uint2(w0, w1);
+    }
+  }
+}
+
 // Direct window counts: this lane sums the 2r+1 column vectors of its window.
 // Bytes are summed `batch` columns at a time (no byte overflows) and then
 // widened to 16-bit fields.
@@ -637,6 +720,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                      ? (9 * span) / ((12 * (64 + 2 * r)) / 64 + 6)
                      : 1;
   const int maxrounds = ADAPT ? (3 * bits) / kTierLevels + 1 : (stop + kTierLevels - 1) / kTierLevels;
+  Band band;
+  if (a.mfma) band_init(band, span, lane);
   int gr = 0;
 
   for (int64_t y = yb; y < ye; ++y) {
@@ -670,7 +755,28 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         int groups = 0;
         for (uint64_t t = pend; t && groups <= a.max_groups; ++groups)
           t &= ~ballot(slot == readlane(slot, __builtin_ctzll(t)));
-        if (groups <= a.max_groups) {
+        if (groups <= a.max_groups && a.mfma) {
+          for (uint64_t t = pend; t;) {
+            const int s = readlane(slot, __builtin_ctzll(t));
+            const uint64_t m = ballot(slot == s) & t;
+            t &= ~m;
+            mfma_group(band, slots, cp16, a.cp, s, m, wv * 64, lane, scr);
+          }
+          wave_sync_lds();
+          if ((pend >> lane) & 1) {
+            const uint4 u0 = *(const uint4*)(scr + lane * 32);
+            const uint4 u1 = *(const uint4*)(scr + lane * 32 + 16);
+            W[0] = u0.x;
+            W[1] = u0.y;
+            W[2] = u0.z;
+            W[3] = u0.w;
+            W[4] = u1.x;
+            W[5] = u1.y;
+            W[6] = u1.z;
+            W[7] = u1.w;
+          }
+          wave_sync_lds();  // the scratch area is reused below
+        } else if (groups <= a.max_groups) {
           for (uint64_t t = pend; t;) {
             const int s = readlane(slot, __builtin_ctzll(t));
             const uint64_t m = ballot(slot == s) & t;
