@@ -269,7 +269,10 @@ typedef int v4i_t __attribute__((ext_vector_type(4)));
 // D[4(l/16) + v][l % 16] for v = 0..3.  Here A = column counts (node x k),
 // read transposed from the column-major slot by ds_read_b64_tr_b8: lane t of a
 // 16-lane group names half t % 2 of column c0 + t / 2, and receives node t of
-// columns c0 .. c0 + 7.  B = band (k x pixel), built once per tile.
+// columns c0 .. c0 + 7.  B = band (k x pixel), built once per tile.  The sum
+// runs over k in any order, so k = 16g + 8h + j of a 64-column step stands for
+// column 32h + 8g + j: each of the two reads of a step then covers 32
+// consecutive columns (512 contiguous bytes) across the wave.
 struct Band {
   v4i_t f[3][4];  // [64-column step][16-pixel tile]
   int steps;
@@ -282,25 +285,32 @@ __device__ __forceinline__ void band_init(Band& bd, int span, int lane) {
   for (int ks = 0; ks < 3; ++ks)
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      // bytes b with 0 <= k - p < span, k = 64ks + 16g + b, p = 16nt + t
-      const int d = 64 * ks + 16 * (g - nt) - t;
-      const int blo = -d < 0 ? 0 : (-d > 16 ? 16 : -d);
-      const int bhi = span - d < 0 ? 0 : (span - d > 16 ? 16 : span - d);
       uint32_t w[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        uint32_t x = 0;
+      for (int h = 0; h < 2; ++h) {
+        // bytes j of half h with 0 <= column - p < span, column = 64ks + 32h
+        // + 8g + j, p = 16nt + t
+        const int d = 64 * ks + 32 * h + 8 * g - 16 * nt - t;
+        const int jlo = -d < 0 ? 0 : (-d > 8 ? 8 : -d);
+        const int jhi = span - d < 0 ? 0 : (span - d > 8 ? 8 : span - d);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) x |= (4 * q + b >= blo && 4 * q + b < bhi) ? 1u << (8 * b) : 0u;
-        w[q] = x;
+        for (int q = 0; q < 2; ++q) {
+          uint32_t x = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            x |= (4 * q + b >= jlo && 4 * q + b < jhi) ? 1u << (8 * b) : 0u;
+          w[2 * h + q] = x;
+        }
       }
       bd.f[ks][nt] = v4i_t{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
     }
 }
 
-// Counts of slot s for the pixels of `m` into the wave's staging area
-// (pixel p at p * 32 bytes, in the packed layout wsel reads).  All 64 lanes
-// must call it.
+// Counts of slot s for the pixels of `m` into the wave's staging area, in
+// the packed layout wsel reads: the two words of node rows 4g..4g+3 of pixel
+// p at g * 512 + p * 8 bytes, so that 16 lanes of one row group store, and
+// all 64 lanes load, consecutive 8-byte words (no bank conflicts).  All 64
+// lanes must call it.
 __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots, size_t cp16,
                                            int cp, int s, uint64_t m, int wbase, int lane,
                                            uint8_t* stage) {
@@ -314,7 +324,7 @@ __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots,
       v4i_t a;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        int c = cb + 64 * ks + 16 * g + 8 * h + (t >> 1);
+        int c = cb + 64 * ks + 32 * h + 8 * g + (t >> 1);
         c = c < cp - 1 ? c : cp - 1;  // past the strip: band weight 0
         const v2i_t rr = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
             (v2i_t __attribute__((address_space(3)))*)(sb + (size_t)c * 16 + 8 * (t & 1)));
@@ -332,7 +342,7 @@ __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots,
     if ((m >> p) & 1) {
       const uint32_t w0 = (uint32_t)acc[nt][0] | ((uint32_t)acc[nt][2] << 16);
       const uint32_t w1 = (uint32_t)acc[nt][1] | ((uint32_t)acc[nt][3] << 16);
-      *(uint2*)(stage + p * 32 + 8 * g) = make_uint2(w0, w1);
+      *(uint2*)(stage + g * 512 + p * 8) = make_uint2(w0, w1);
     }
   }
 }
@@ -764,16 +774,12 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           }
           wave_sync_lds();
           if ((pend >> lane) & 1) {
-            const uint4 u0 = *(const uint4*)(scr + lane * 32);
-            const uint4 u1 = *(const uint4*)(scr + lane * 32 + 16);
-            W[0] = u0.x;
-            W[1] = u0.y;
-            W[2] = u0.z;
-            W[3] = u0.w;
-            W[4] = u1.x;
-            W[5] = u1.y;
-            W[6] = u1.z;
-            W[7] = u1.w;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+              const uint2 u = *(const uint2*)(scr + g * 512 + lane * 8);
+              W[2 * g] = u.x;
+              W[2 * g + 1] = u.y;
+            }
           }
           wave_sync_lds();  // the scratch area is reused below
         } else if (groups <= a.max_groups) {
