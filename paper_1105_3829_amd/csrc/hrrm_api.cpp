@@ -76,9 +76,9 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   t.min_group = 2;
   t.nslots = 0;
   t.lds_budget = 80 * 1024;  // two workgroups per CU
-  // 16-bit windows of at most 49 values (r <= 3 in 2-D, r = 1 in 3-D) count
-  // their deeper tiers from the raw values; 8-bit trees are shallow enough
-  // that held subtrees always win
+  // 16-bit windows of at most 49 values (r <= 3 in 2-D, r = 1 in 3-D; 2-D
+  // r = 4 below as well) count their deeper tiers from the raw values; 8-bit
+  // trees are shallow enough that held subtrees always win
   t.raw_window = bytes == 2 ? 49 : 0;
   const int64_t strips = (w + kBlock - 1) / kBlock;
   int64_t rows;
@@ -86,7 +86,9 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..127):
     // counting a tier for all 64 pixels of a wave at once (matrix cores, or
     // prefix sums past 127-value columns) pays off for more distinct subtrees
-    // per wave the wider the window; narrow windows sum per lane.  16-bit windows run two workgroups per
+    // per wave the wider the window; narrow windows sum per lane.  8-bit
+    // uniform trees take tall segments at every radius (two waves of tiles on
+    // an 8192^2 image).  16-bit windows run two workgroups per
     // CU with short segments up to r = 63; from r = 64 smooth images need
     // more slots than 80 KB holds (the churn grows with the segment) and run
     // one workgroup per CU with the whole 160 KB and tall segments (4x faster
@@ -101,9 +103,19 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
       if (r >= 64) {
         t.lds_budget = kLdsLimit;
         rows = 128;
+      } else if (r <= 4 && !adaptive) {
+        // windows of at most 81 values: every deeper tier counted raw, so
+        // slot 0 is the only slot in use and three workgroups share a CU
+        t.lds_budget = kLdsThird;
+        t.raw_window = 81;
+        rows = 43;
       } else {
-        rows = r <= 3 ? 32 : r <= 5 ? 64 : r <= 31 ? 48 : 24;
+        rows = r <= 5 ? 64 : r <= 31 ? 48 : 24;
       }
+    } else if (!adaptive) {
+      // 8-bit trees need at most 17 slots: three workgroups per CU
+      t.lds_budget = kLdsThird;
+      rows = 171;
     } else {
       rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
     }
@@ -112,8 +124,9 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     // medians of 125-value cubes spread over more deep subtrees than 80 KB
     // of slots hold: the whole LDS pays there)
     t.max_groups = r <= 3 ? 0 : 2;
-    rows = r <= 1 ? 32 : r == 2 ? 256 : r <= 3 ? 64 : 256;
+    rows = r <= 1 ? 16 : r == 2 ? 256 : r <= 3 ? 64 : 256;
     if (r == 2 && bytes == 2) t.lds_budget = kLdsLimit;
+    if (r <= 1) t.lds_budget = kLdsThird;  // 27-value cubes: counted raw below tier 1
   } else {
     // adaptive volumes: more distinct subtrees per row, so shorter segments
     // (fewer rows walking the same slots) and per-lane sums past one group
@@ -122,9 +135,10 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
   }
   // an image filtered on its own keeps at least two tiles per workgroup slot
-  // of the GPU (256 CUs, 1 or 2 workgroups each) when it allows it; in a batch
-  // the other images fill the GPU
-  const int64_t want = t.lds_budget > kLdsLimit / 2 ? 512 : 1024;
+  // of the GPU (256 CUs, 1 to 3 workgroups each) when it allows it; in a
+  // batch the other images fill the GPU
+  const int64_t per_cu = t.lds_budget > kLdsLimit / 2 ? 1 : t.lds_budget > kLdsThird ? 2 : 3;
+  const int64_t want = 2 * 256 * per_cu;
   const int64_t fill = (strips * h * d + want - 1) / want;
   if (fill_gpu && strips * ((h + rows - 1) / rows) * d < want)
     rows = std::max<int64_t>(8, std::min(rows, fill));

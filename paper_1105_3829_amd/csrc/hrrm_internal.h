@@ -13,6 +13,10 @@ constexpr int kDenseNodes = 255;     // left-node counters of a full 8-bit tree
 constexpr int kHash = 128;           // slot hash-table entries (power of two)
 constexpr int kMaxSlots = 64;        // tier slots per workgroup, slot 0 included
 constexpr int kLdsLimit = 160 * 1024;
+// Largest LDS budget at which three workgroups share one CU (LDS is granted
+// in blocks: measured on MI355X, 53,536 bytes per workgroup let three in and
+// 53,856 did not).
+constexpr int kLdsThird = 53760;
 constexpr int kRawWindow = 81;       // (2r+1)^D up to this: missing subtrees counted raw
 
 // Bytes of one wave's scratch area in the tiered kernel: the column vectors

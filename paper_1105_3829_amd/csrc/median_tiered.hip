@@ -199,14 +199,19 @@ __device__ __forceinline__ uint4 smask(const TopoNode* st, int dep, int stop, in
 }
 
 // Count of node q (0..14) from the packed window counts: word 2i holds nodes
-// 4i and 4i+2, word 2i+1 nodes 4i+1 and 4i+3 (16-bit fields).
-__device__ __forceinline__ uint32_t wsel(const uint32_t (&W)[8], int q) {
+// 4i and 4i+2, word 2i+1 nodes 4i+1 and 4i+3 (16-bit fields).  The words come
+// in by value: selecting between elements of an array argument lets the
+// compiler turn the selects into one dynamically indexed load, which keeps the
+// caller's counts in private (scratch) memory.
+__device__ __forceinline__ uint32_t wsel(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
+                                         uint32_t w4, uint32_t w5, uint32_t w6, uint32_t w7,
+                                         int q) {
   const int i = q >> 2;
   const bool odd = q & 1;
-  const uint32_t a0 = odd ? W[1] : W[0];
-  const uint32_t a1 = odd ? W[3] : W[2];
-  const uint32_t a2 = odd ? W[5] : W[4];
-  const uint32_t a3 = odd ? W[7] : W[6];
+  const uint32_t a0 = odd ? w1 : w0;
+  const uint32_t a1 = odd ? w3 : w2;
+  const uint32_t a2 = odd ? w5 : w4;
+  const uint32_t a3 = odd ? w7 : w6;
   const uint32_t b0 = (i & 1) ? a1 : a0;
   const uint32_t b1 = (i & 1) ? a3 : a2;
   const uint32_t c = (i & 2) ? b1 : b0;
@@ -836,7 +841,8 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
 #pragma unroll
         for (int k = 0; k < kTierLevels; ++k) {
           if (k < lv) {
-            const uint32_t wl = k == 0 ? (W[0] & 0xffffu) : wsel(W, p - 1);
+            const uint32_t wl = k == 0 ? (W[0] & 0xffffu)
+                                        : wsel(W[0], W[1], W[2], W[3], W[4], W[5], W[6], W[7], p - 1);
             const bool right = acc + wl <= K;
             acc += right ? wl : 0u;
             p = 2 * p + (right ? 1 : 0);
@@ -867,7 +873,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
               split = lo + (1 << (bits - 1 - depth));
               lleaf = rleaf = depth + 1 >= bits;
             }
-            const uint32_t wl = wsel(W, p - 1);
+            const uint32_t wl = wsel(W[0], W[1], W[2], W[3], W[4], W[5], W[6], W[7], p - 1);
             const bool left = acc + wl > K;
             bool leaf;
             if (left) {
@@ -1111,8 +1117,13 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   }
 }
 
-template <typename T, bool ADAPT, bool D3>
-__global__ __launch_bounds__(kBlock) void k_median_tiered(MedianArgs a) {
+// WPE = 3 asks for three waves per SIMD (at most 168 registers per lane), so
+// that three workgroups with budgets of kLdsThird bytes share a CU; WPE = 1
+// leaves the register allocation free (workgroups with larger budgets run at
+// most two per CU anyway).
+template <typename T, bool ADAPT, bool D3, int WPE>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_median_tiered(
+    MedianArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int rest = bid / a.strips;
@@ -1176,7 +1187,10 @@ __global__ void k_zero_counter(uint32_t* counter) {
 
 template <typename T, bool ADAPT, bool D3>
 hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
-  auto kern = k_median_tiered<T, ADAPT, D3>;
+  auto kern = k_median_tiered<T, ADAPT, D3, 1>;
+  if constexpr (!ADAPT) {
+    if (lds <= (size_t)kLdsThird) kern = k_median_tiered<T, ADAPT, D3, 3>;
+  }
   hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;

@@ -49,13 +49,13 @@ def test_u8_large_radius(hrrm, r):
     _check2d(hrrm, img, r)
 
 
-@pytest.mark.parametrize("r", [0, 1, 2, 5, 15, 31, 32, 50])
+@pytest.mark.parametrize("r", [0, 1, 2, 3, 4, 5, 15, 31, 32, 50])
 def test_u16_xray_radii(hrrm, r):
     img = datagen.xray_u16(180, 290, seed=20 + r)
     _check2d(hrrm, img, r)
 
 
-@pytest.mark.parametrize("r", [1, 3, 7, 15])
+@pytest.mark.parametrize("r", [1, 3, 4, 7, 15])
 def test_u16_full_range_many_subtrees(hrrm, r):
     # i.i.d. full-range values: medians scatter over many deep subtrees, which
     # exercises slot eviction and the direct-count path
@@ -165,7 +165,7 @@ def test_repeatable(hrrm):
         assert np.array_equal(to_host(hrrm.median2d(d, 9)), a)
 
 
-@pytest.mark.parametrize("r", [5, 15, 50])
+@pytest.mark.parametrize("r", [1, 4, 5, 15, 50])
 def test_c1_full_size_sampled(hrrm, r):
     # the headline workload at full size: u16 4096^2, both variants, default
     # tiles (the launch the benchmark times); the oracle checks 20000 sampled
