@@ -51,6 +51,7 @@ constexpr int kMissGroups = 8;  // subtree groups per wave and round offered to 
 constexpr int kMissCap = kMissGroups * kWaves;  // misses queued per round
 constexpr int kSlotLanes = 4;   // lanes that must share a subtree to claim a slot in a wave
                                 // that wants more than kMissGroups different subtrees
+constexpr int kRebRows = 8;     // window rows a slot rebuild loads per column before using any
 constexpr int kSmap = 16 + 256 + 4096;  // roots of tiers 2..4 of a 16-bit uniform tree
 constexpr uint32_t kNone = 0xffu;
 
@@ -960,32 +961,50 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         const int nreb = ts->reb_n;
         if (nreb > 0) {
           // Rebuild the new slots from the window's raw values (each thread
-          // owns its columns: no atomics, no barrier between clear and fill).
-          for (int lc = tid; lc < ncols; lc += kBlock) {
-            const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
-            for (int i = 0; i < nreb; ++i) {
-              const int rs = ts->reb[i][0], rlo = ts->reb[i][2];
-              const int rdep = ts->reb[i][3];
-              const int rhi = ts->hi[rs];
-              const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
-              uint4 c = make_uint4(0u, 0u, 0u, 0u);
-              for (int dz = -zr; dz <= zr; ++dz) {
-                const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
-#pragma unroll 4
-                for (int j = -r; j <= r; ++j) {
-                  const int v = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
-                  if (v >= rlo && v <= rhi) {
-                    if constexpr (ADAPT) {
-                      int nx;
-                      c = add4(c, smask(stopo + rs * 16, rdep, stop, v, &nx));
-                    } else {
-                      c = add4(c, and4(ts->lut[nib(v, rdep, bits)], lim));
-                    }
+          // owns columns tid and tid + 256: no atomics, no barrier between
+          // clear and fill).  The rows of both columns are loaded kRebRows at
+          // a time before any is used, so their latencies overlap.
+          const bool two = tid + kBlock < ncols;
+          const int64_t cx0 = clampi(x0 - r - 1 + tid, a.w - 1);
+          const int64_t cx1 = clampi(x0 - r - 1 + tid + kBlock, a.w - 1);
+          for (int i = 0; i < nreb; ++i) {
+            const int rs = ts->reb[i][0], rlo = ts->reb[i][2];
+            const int rdep = ts->reb[i][3];
+            const int rhi = ts->hi[rs];
+            const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+            auto tmask = [&](int v) -> uint4 {
+              if constexpr (ADAPT) {
+                int nx;
+                return smask(stopo + rs * 16, rdep, stop, v, &nx);
+              } else {
+                return and4(ts->lut[nib(v, rdep, bits)], lim);
+              }
+            };
+            uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
+            for (int dz = -zr; dz <= zr; ++dz) {
+              const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+              const T* p0 = src + zz * a.sss + cx0;
+              const T* p1 = src + zz * a.sss + cx1;
+              for (int j0 = -r; j0 <= r; j0 += kRebRows) {
+                int v0[kRebRows], v1[kRebRows];
+#pragma unroll
+                for (int k = 0; k < kRebRows; ++k) {
+                  // rows past the window repeat its last row and are skipped
+                  const int64_t yy = clampi(y + (j0 + k <= r ? j0 + k : r), a.h - 1);
+                  v0[k] = p0[yy * a.srs];
+                  v1[k] = two ? (int)p1[yy * a.srs] : -1;
+                }
+#pragma unroll
+                for (int k = 0; k < kRebRows; ++k) {
+                  if (j0 + k <= r) {
+                    if (v0[k] >= rlo && v0[k] <= rhi) c0 = add4(c0, tmask(v0[k]));
+                    if (v1[k] >= rlo && v1[k] <= rhi) c1 = add4(c1, tmask(v1[k]));
                   }
                 }
               }
-              vec(slots, cp16, rs, lc) = c;
             }
+            vec(slots, cp16, rs, tid) = c0;
+            if (two) vec(slots, cp16, rs, tid + kBlock) = c1;
           }
           __syncthreads();
         }
