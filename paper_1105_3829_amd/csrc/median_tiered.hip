@@ -981,25 +981,30 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
               }
             };
             uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
-            for (int dz = -zr; dz <= zr; ++dz) {
-              const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
-              const T* p0 = src + zz * a.sss + cx0;
-              const T* p1 = src + zz * a.sss + cx1;
-              for (int j0 = -r; j0 <= r; j0 += kRebRows) {
-                int v0[kRebRows], v1[kRebRows];
+            // the (2zr + 1) x span window rows of the columns, slice-major;
+            // (dz, j) walks them kRebRows at a time
+            const int nrows = (2 * zr + 1) * span;
+            int dz = -zr, j = -r;
+            for (int q0 = 0; q0 < nrows; q0 += kRebRows) {
+              int v0[kRebRows], v1[kRebRows];
 #pragma unroll
-                for (int k = 0; k < kRebRows; ++k) {
-                  // rows past the window repeat its last row and are skipped
-                  const int64_t yy = clampi(y + (j0 + k <= r ? j0 + k : r), a.h - 1);
-                  v0[k] = p0[yy * a.srs];
-                  v1[k] = two ? (int)p1[yy * a.srs] : -1;
+              for (int k = 0; k < kRebRows; ++k) {
+                // rows past the window (slice zr + 1 onwards) are clamped into
+                // the volume, loaded and skipped
+                const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+                const int64_t off = zz * a.sss + clampi(y + j, a.h - 1) * a.srs;
+                v0[k] = src[off + cx0];
+                v1[k] = two ? (int)src[off + cx1] : -1;
+                if (++j > r) {
+                  j = -r;
+                  ++dz;
                 }
+              }
 #pragma unroll
-                for (int k = 0; k < kRebRows; ++k) {
-                  if (j0 + k <= r) {
-                    if (v0[k] >= rlo && v0[k] <= rhi) c0 = add4(c0, tmask(v0[k]));
-                    if (v1[k] >= rlo && v1[k] <= rhi) c1 = add4(c1, tmask(v1[k]));
-                  }
+              for (int k = 0; k < kRebRows; ++k) {
+                if (q0 + k < nrows) {
+                  if (v0[k] >= rlo && v0[k] <= rhi) c0 = add4(c0, tmask(v0[k]));
+                  if (v1[k] >= rlo && v1[k] <= rhi) c1 = add4(c1, tmask(v1[k]));
                 }
               }
             }
