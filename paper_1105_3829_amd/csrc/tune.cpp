@@ -202,12 +202,13 @@ int autotune(Context* c, const void* d_sample, int dtype, int r, int variant, in
   if (rc == HRRM_OK) rc = time_cfg(cur, &cur_ms);
   int tried = 1;
   if (rc == HRRM_OK) {
-    const bool tiered_kernel = bytes == 2;
+    const bool tiered_kernel = bytes == 2 || cur.tiered_u8 != 0;
     std::vector<std::pair<int, std::vector<int>>> axes = {
-        {0, {16, 32, 64, 128, 256}},                        // seg_rows
-        {4, {48 * 1024, 64 * 1024, 80 * 1024, 112 * 1024, 160 * 1024}},  // lds_budget
+        {0, {16, 32, 64, 128, 256}},  // seg_rows
+        // lds_budget: three workgroups per CU up to kLdsThird, two up to 80 KB
+        {4, {48 * 1024, kLdsThird, 64 * 1024, 80 * 1024, 112 * 1024, 160 * 1024}},
     };
-    if (tiered_kernel || adaptive) axes.push_back({3, {0, 1, 2, 4, 8}});  // max_groups
+    if (tiered_kernel || adaptive) axes.push_back({3, {0, 1, 2, 4, 8, 64}});  // max_groups
     else axes.push_back({2, {1, 2, 4, 8}});                               // min_group
     if (bytes == 1) axes.push_back({5, {0, 1}});                          // tiered_u8
     axes.push_back({6, {0, 9, 27, 49, 81}});                              // raw_window
