@@ -105,17 +105,19 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
         rows = 128;
       } else if (r <= 4 && !adaptive) {
         // windows of at most 81 values: every deeper tier counted raw, so
-        // slot 0 is the only slot in use and three workgroups share a CU
-        t.lds_budget = kLdsThird;
+        // slot 0 is the only slot in use and six workgroups share a CU
+        t.lds_budget = kLdsSixth;
         t.raw_window = 81;
-        rows = 43;
+        rows = r <= 1 ? 16 : 8;
       } else {
         rows = r <= 5 ? 64 : r <= 31 ? 48 : 24;
       }
     } else if (!adaptive) {
-      // 8-bit trees need at most 17 slots: three workgroups per CU
-      t.lds_budget = kLdsThird;
-      rows = 171;
+      // 8-bit trees need at most 17 slots: three workgroups per CU, four
+      // where no subtree is counted wave-wide (the build without the matrix
+      // cores has the registers for it)
+      t.lds_budget = t.max_groups == 0 ? kLdsQuarter : kLdsThird;
+      rows = t.max_groups == 0 ? 128 : 171;
     } else {
       rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
     }
@@ -124,9 +126,16 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     // medians of 125-value cubes spread over more deep subtrees than 80 KB
     // of slots hold: the whole LDS pays there)
     t.max_groups = r <= 3 ? 0 : 2;
-    rows = r <= 1 ? 16 : r == 2 ? 256 : r <= 3 ? 64 : 256;
+    rows = r == 2 ? 256 : r <= 3 ? 64 : 256;
     if (r == 2 && bytes == 2) t.lds_budget = kLdsLimit;
-    if (r <= 1) t.lds_budget = kLdsThird;  // 27-value cubes: counted raw below tier 1
+    if (r <= 1 && bytes == 2) {
+      // 27-value cubes: counted raw below tier 1, six workgroups per CU
+      t.lds_budget = kLdsSixth;
+      rows = 8;
+    } else if (r <= 1) {
+      t.lds_budget = kLdsThird;
+      rows = 16;
+    }
   } else {
     // adaptive volumes: more distinct subtrees per row, so shorter segments
     // (fewer rows walking the same slots) and per-lane sums past one group
@@ -135,10 +144,9 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
   }
   // an image filtered on its own keeps at least two tiles per workgroup slot
-  // of the GPU (256 CUs, 1 to 3 workgroups each) when it allows it; in a
+  // of the GPU (256 CUs, 1 to 6 workgroups each) when it allows it; in a
   // batch the other images fill the GPU
-  const int64_t per_cu = t.lds_budget > kLdsLimit / 2 ? 1 : t.lds_budget > kLdsThird ? 2 : 3;
-  const int64_t want = 2 * 256 * per_cu;
+  const int64_t want = 2 * 256 * (int64_t)tiered_per_cu(t.lds_budget, t.max_groups);
   const int64_t fill = (strips * h * d + want - 1) / want;
   if (fill_gpu && strips * ((h + rows - 1) / rows) * d < want)
     rows = std::max<int64_t>(8, std::min(rows, fill));

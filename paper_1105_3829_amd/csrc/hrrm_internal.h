@@ -13,10 +13,25 @@ constexpr int kDenseNodes = 255;     // left-node counters of a full 8-bit tree
 constexpr int kHash = 128;           // slot hash-table entries (power of two)
 constexpr int kMaxSlots = 64;        // tier slots per workgroup, slot 0 included
 constexpr int kLdsLimit = 160 * 1024;
-// Largest LDS budget at which three workgroups share one CU (LDS is granted
-// in blocks: measured on MI355X, 53,536 bytes per workgroup let three in and
-// 53,856 did not).
+// Largest LDS budgets at which three, four or six workgroups share one CU.
+// LDS is granted in blocks of 1,280 bytes (measured on MI355X: 53,536 bytes
+// per workgroup let three in and 53,856 did not).
 constexpr int kLdsThird = 53760;
+constexpr int kLdsQuarter = 40960;
+constexpr int kLdsSixth = 26880;
+
+// Workgroups of the tiered kernel that share one CU at this LDS budget; past
+// kLdsThird the build that runs them has registers for three waves per SIMD,
+// and for four or six only when it counts no subtree wave-wide
+// (max_groups = 0).
+constexpr int tiered_per_cu(int lds_budget, int max_groups) {
+  return lds_budget > kLdsLimit / 2   ? 1
+         : lds_budget > kLdsThird     ? 2
+         : lds_budget > kLdsQuarter   ? 3
+         : max_groups > 0             ? 3
+         : lds_budget > kLdsSixth     ? 4
+                                      : 6;
+}
 constexpr int kRawWindow = 81;       // (2r+1)^D up to this: missing subtrees counted raw
 
 // Bytes of one wave's scratch area in the tiered kernel: the column vectors

@@ -601,8 +601,10 @@ __device__ void assign_slots(TS* ts, int nmiss, int stamp, int nslots, TopoNode*
 
 // One workgroup tile: output columns [strip*256, strip*256 + 256) of rows
 // [seg*seg_rows, seg*seg_rows + seg_rows) of slice z.  `lds` is the dynamic LDS
-// of the workgroup (slots, tier state, per-wave scratch).
-template <typename T, bool ADAPT, bool D3>
+// of the workgroup (slots, tier state, per-wave scratch).  MF = false leaves
+// the matrix-core counts (and the 48 registers of their band) out; such
+// builds serve only launches that count no subtree wave-wide (max_groups 0).
+template <typename T, bool ADAPT, bool D3, bool MF = true>
 __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int strip, int seg,
                                           int64_t z) {
   const T* __restrict__ src = (const T*)a.src;
@@ -737,7 +739,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
                      : 1;
   const int maxrounds = ADAPT ? (3 * bits) / kTierLevels + 1 : (stop + kTierLevels - 1) / kTierLevels;
   Band band;
-  if (a.mfma) band_init(band, span, lane);
+  if (MF && a.mfma) band_init(band, span, lane);
   int gr = 0;
 
   for (int64_t y = yb; y < ye; ++y) {
@@ -771,7 +773,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         int groups = 0;
         for (uint64_t t = pend; t && groups <= a.max_groups; ++groups)
           t &= ~ballot(slot == readlane(slot, __builtin_ctzll(t)));
-        if (groups <= a.max_groups && a.mfma) {
+        if (MF && groups <= a.max_groups && a.mfma) {
           for (uint64_t t = pend; t;) {
             const int s = readlane(slot, __builtin_ctzll(t));
             const uint64_t m = ballot(slot == s) & t;
@@ -1142,16 +1144,18 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
 }
 
 // WPE = 3 asks for three waves per SIMD (at most 168 registers per lane), so
-// that three workgroups with budgets of kLdsThird bytes share a CU; WPE = 1
-// leaves the register allocation free (workgroups with larger budgets run at
-// most two per CU anyway).
+// that three workgroups with budgets of kLdsThird bytes share a CU; WPE = 4
+// and 6 (at most 128 / 85 registers, no matrix-core counts) let four or six
+// workgroups of kLdsQuarter / kLdsSixth bytes share one; WPE = 1 leaves the
+// register allocation free (workgroups with larger budgets run at most two
+// per CU anyway).
 template <typename T, bool ADAPT, bool D3, int WPE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_median_tiered(
     MedianArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int rest = bid / a.strips;
-  tile_body<T, ADAPT, D3>(a, lds, bid % a.strips, rest % a.segs, rest / a.segs);
+  tile_body<T, ADAPT, D3, (WPE <= 3)>(a, lds, bid % a.strips, rest % a.segs, rest / a.segs);
 }
 
 // Persistent batched launch: every workgroup repeatedly takes the next tile
@@ -1213,7 +1217,12 @@ template <typename T, bool ADAPT, bool D3>
 hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
   auto kern = k_median_tiered<T, ADAPT, D3, 1>;
   if constexpr (!ADAPT) {
-    if (lds <= (size_t)kLdsThird) kern = k_median_tiered<T, ADAPT, D3, 3>;
+    if (lds <= (size_t)kLdsSixth && a.max_groups == 0)
+      kern = k_median_tiered<T, ADAPT, D3, 6>;
+    else if (lds <= (size_t)kLdsQuarter && a.max_groups == 0)
+      kern = k_median_tiered<T, ADAPT, D3, 4>;
+    else if (lds <= (size_t)kLdsThird)
+      kern = k_median_tiered<T, ADAPT, D3, 3>;
   }
   hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;

@@ -205,8 +205,10 @@ int autotune(Context* c, const void* d_sample, int dtype, int r, int variant, in
     const bool tiered_kernel = bytes == 2 || cur.tiered_u8 != 0;
     std::vector<std::pair<int, std::vector<int>>> axes = {
         {0, {16, 32, 64, 128, 256}},  // seg_rows
-        // lds_budget: three workgroups per CU up to kLdsThird, two up to 80 KB
-        {4, {48 * 1024, kLdsThird, 64 * 1024, 80 * 1024, 112 * 1024, 160 * 1024}},
+        // lds_budget: six, four, three workgroups per CU up to kLdsSixth,
+        // kLdsQuarter, kLdsThird (the first two only without wave-wide
+        // counts), two up to 80 KB
+        {4, {kLdsSixth, kLdsQuarter, kLdsThird, 64 * 1024, 80 * 1024, 112 * 1024, 160 * 1024}},
     };
     if (tiered_kernel || adaptive) axes.push_back({3, {0, 1, 2, 4, 8, 64}});  // max_groups
     else axes.push_back({2, {1, 2, 4, 8}});                               // min_group
