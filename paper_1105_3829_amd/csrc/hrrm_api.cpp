@@ -76,9 +76,9 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   t.min_group = 2;
   t.nslots = 0;
   t.lds_budget = 80 * 1024;  // two workgroups per CU
-  // 16-bit windows of at most 49 values (r <= 3 in 2-D, r = 1 in 3-D; 2-D
-  // r = 4 below as well) count their deeper tiers from the raw values; 8-bit
-  // trees are shallow enough that held subtrees always win
+  // 16-bit windows of at most 49 values (r <= 3 in 2-D, r = 1 in 3-D; and
+  // below, uniform 2-D r <= 5 and 3-D r = 2) count their deeper tiers from
+  // the raw values; 8-bit trees are shallow enough that held subtrees win
   t.raw_window = bytes == 2 ? 49 : 0;
   const int64_t strips = (w + kBlock - 1) / kBlock;
   int64_t rows;
@@ -98,16 +98,16 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     if (bytes == 2)
       t.max_groups = r <= 7 ? 0 : r <= 15 ? 1 : r <= 31 ? 4 : 64;
     else
-      t.max_groups = r <= 4 ? 0 : r <= 8 ? 1 : 64;
+      t.max_groups = r <= 8 ? 0 : 64;
     if (bytes == 2) {
       if (r >= 64) {
         t.lds_budget = kLdsLimit;
         rows = 128;
-      } else if (r <= 4 && !adaptive) {
-        // windows of at most 81 values: every deeper tier counted raw, so
+      } else if (r <= 5 && !adaptive) {
+        // windows of at most 121 values: every deeper tier counted raw, so
         // slot 0 is the only slot in use and six workgroups share a CU
         t.lds_budget = kLdsSixth;
-        t.raw_window = 81;
+        t.raw_window = (2 * r + 1) * (2 * r + 1);
         rows = r <= 1 ? 16 : 8;
       } else {
         rows = r <= 5 ? 64 : r <= 31 ? 48 : 24;
@@ -122,15 +122,15 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
       rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
     }
   } else if (!adaptive) {
-    // measured on a 512 x 512 x 256 16-bit volume, r = 1..7 (at r = 2 the
-    // medians of 125-value cubes spread over more deep subtrees than 80 KB
-    // of slots hold: the whole LDS pays there)
+    // measured on a 512 x 512 x 256 16-bit volume, r = 1..7: 16-bit cubes of
+    // up to 125 values count every deeper tier raw at six workgroups per CU
+    // (at r = 2 the medians spread over more deep subtrees than even 160 KB
+    // of slots hold well)
     t.max_groups = r <= 3 ? 0 : 2;
     rows = r == 2 ? 256 : r <= 3 ? 64 : 256;
-    if (r == 2 && bytes == 2) t.lds_budget = kLdsLimit;
-    if (r <= 1 && bytes == 2) {
-      // 27-value cubes: counted raw below tier 1, six workgroups per CU
+    if (r <= 2 && bytes == 2) {
       t.lds_budget = kLdsSixth;
+      t.raw_window = (2 * r + 1) * (2 * r + 1) * (2 * r + 1);
       rows = 8;
     } else if (r <= 1) {
       t.lds_budget = kLdsThird;

@@ -104,7 +104,8 @@ def test_adaptive(hrrm, kind, r, variant):
 
 
 @pytest.mark.parametrize("dt,r", [(np.uint16, 0), (np.uint16, 1), (np.uint16, 2), (np.uint16, 3),
-                                  (np.uint8, 5), (np.uint8, 7), (np.uint16, 7)])
+                                  (np.uint8, 1), (np.uint8, 2), (np.uint8, 5), (np.uint8, 7),
+                                  (np.uint16, 7)])
 def test_3d(hrrm, dt, r):
     if dt == np.uint16:
         vol = datagen.xray_volume_u16(5, 40, 270, seed=50 + r)
@@ -198,17 +199,19 @@ def test_c2_full_size_sampled(hrrm, r):
         assert np.array_equal(got[ys, xs], want), variant
 
 
-def test_c3_full_size_sampled(hrrm):
-    # u16 512x512x256 volume with impulses at full size, r = 7
+@pytest.mark.parametrize("r", [1, 2, 7])
+def test_c3_full_size_sampled(hrrm, r):
+    # u16 512x512x256 volume with impulses at full size, default tiles (r = 1
+    # and 2 count every deeper tier raw at six workgroups per CU)
     vol = datagen.xray_volume_u16(256, 512, 512, seed=3)
     d = to_dev(vol)
     g = np.random.default_rng(3)
     zs = np.concatenate([g.integers(0, 256, 3000), np.zeros(200, int), np.full(200, 255)])
     ys = g.integers(0, 512, zs.size)
     xs = g.integers(0, 512, zs.size)
-    want = oracle.rank3d_at(vol, 7, xs, ys, zs)
-    announce("c3 full r=7")
-    got = to_host(hrrm.median3d(d, 7))
+    want = oracle.rank3d_at(vol, r, xs, ys, zs)
+    announce("c3 full", "r=%d" % r)
+    got = to_host(hrrm.median3d(d, r))
     assert np.array_equal(got[zs, ys, xs], want)
 
 
