@@ -24,13 +24,19 @@ namespace hrrm {
 
 namespace {
 constexpr int kBatchCap = 4096;           // images per batch
-// dynamic LDS per workgroup: with the kernel's few static bytes two workgroups fit a CU
+// dynamic LDS per workgroup: with the kernel's few static bytes two (heavy
+// class) or four (light class) workgroups fit a CU
 constexpr size_t kBatchLds = 80 * 1024 - 256;
+constexpr size_t kBatchLightLds = kLdsQuarter - 256;
 constexpr int kBatchMaxR = 127;
 }  // namespace
 
-constexpr size_t kDescOffset = 256;  // descriptors start here in the device buffer
-constexpr size_t kBatchBytes = kDescOffset + sizeof(BatchImage) * kBatchCap;
+// Device buffer of one stream: the light and heavy classes' 8 work counters at
+// bytes 0 and 32, their image counts at bytes 64 and 68, their descriptors in
+// two fixed regions (the captured launches keep their pointers).
+constexpr size_t kDescOffset = 256;
+constexpr size_t kClassBytes = sizeof(BatchImage) * kBatchCap;
+constexpr size_t kBatchBytes = kDescOffset + 2 * kClassBytes;
 
 BatchStream* Context::batch_for(hipStream_t s) {
   for (auto& b : batch)
@@ -63,17 +69,19 @@ void Context::release_batch() {
   batch.clear();
 }
 
-int batched_grid(int device) {
+int batched_grid(int device, bool light) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       cus <= 0)
     cus = 256;
-  return cus * 2;
+  return cus * (light ? 4 : 2);
 }
 
 int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t stream,
                 bool use_graph) {
-  std::vector<BatchImage> descs;
+  // light class: 16-bit images whose windows are counted raw below tier 1
+  // (no subtree counted wave-wide, only slot 0 in use); heavy class: the rest
+  std::vector<BatchImage> descs, light;
   descs.reserve(count);
   int64_t tiles = 0;
   for (int i = 0; i < count; ++i) {
@@ -109,79 +117,106 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     a.segs = (int32_t)((im.height + a.seg_rows - 1) / a.seg_rows);
     a.ncols = kBlock + 2 * im.r + 1;
     a.cp = (a.ncols + 3) & ~3;
-    const size_t meta = tiered_meta_bytes(im.r, bytes) + 16;
-    const size_t slot_bytes = (size_t)a.cp * 16;
-    int ns = kBatchLds > meta ? (int)((kBatchLds - meta) / slot_bytes) : 0;
-    if (t.nslots > 0) ns = std::min(ns, t.nslots);
-    ns = std::min(ns, kMaxSlots);
-    if (ns < 1) return fail(HRRM_EUNSUPPORTED, "image %d: radius %d does not fit a batch", i, im.r);
-    a.nslots = ns;
     a.min_group = std::max(1, t.min_group);
     a.max_groups = std::max(0, t.max_groups);
     a.raw_window = std::max(0, t.raw_window);
     a.mfma = 2 * im.r + 1 <= 127;  // column counts as signed bytes
+    const size_t meta = tiered_meta_bytes(im.r, bytes) + 16;
+    const size_t slot_bytes = (size_t)a.cp * 16;
+    const int64_t span = 2 * im.r + 1;
+    const int ns_light =
+        kBatchLightLds > meta ? (int)((kBatchLightLds - meta) / slot_bytes) : 0;
+    // (8-bit trees stay heavy: images of mixed content want more slots than
+    // the light LDS holds)
+    const bool is_light = bytes == 2 && a.max_groups == 0 && ns_light >= 1 &&
+                          span * span <= a.raw_window;
+    int ns = is_light ? ns_light : kBatchLds > meta ? (int)((kBatchLds - meta) / slot_bytes) : 0;
+    if (t.nslots > 0) ns = std::min(ns, t.nslots);
+    ns = std::min(ns, kMaxSlots);
+    if (ns < 1) return fail(HRRM_EUNSUPPORTED, "image %d: radius %d does not fit a batch", i, im.r);
+    a.nslots = ns;
     tiles += (int64_t)a.strips * a.segs;
     if (tiles > 0x7fffffff) return fail(HRRM_EUNSUPPORTED, "batch has too many tiles");
-    b.tile_end = tiles;
     b.bytes = bytes;
-    descs.push_back(b);
+    (is_light ? light : descs).push_back(b);
   }
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
-  if (descs.empty()) return HRRM_OK;
-  // longest work first: expensive images (16-bit, larger windows) at the front
-  // of every chunk's range shortens the tail of the launch
-  std::stable_sort(descs.begin(), descs.end(), [](const BatchImage& x, const BatchImage& y) {
-    const double cx = (double)x.args.w * x.args.h * (x.bytes == 2 ? 3.0 : 1.0) *
-                      (1.0 + x.args.r / 16.0);
-    const double cy = (double)y.args.w * y.args.h * (y.bytes == 2 ? 3.0 : 1.0) *
-                      (1.0 + y.args.r / 16.0);
-    return cx > cy;
-  });
-  tiles = 0;
-  for (auto& d : descs) {
-    tiles += (int64_t)d.args.strips * d.args.segs;
-    d.tile_end = tiles;
+  if (descs.empty() && light.empty()) return HRRM_OK;
+  // per class, longest work first: expensive images (16-bit, larger windows)
+  // at the front of every chunk's range shortens the tail of the launch
+  for (auto* v : {&light, &descs}) {
+    std::stable_sort(v->begin(), v->end(), [](const BatchImage& x, const BatchImage& y) {
+      const double cx = (double)x.args.w * x.args.h * (x.bytes == 2 ? 3.0 : 1.0) *
+                        (1.0 + x.args.r / 16.0);
+      const double cy = (double)y.args.w * y.args.h * (y.bytes == 2 ? 3.0 : 1.0) *
+                        (1.0 + y.args.r / 16.0);
+      return cx > cy;
+    });
+    tiles = 0;
+    for (auto& d : *v) {
+      tiles += (int64_t)d.args.strips * d.args.segs;
+      d.tile_end = tiles;
+    }
   }
   BatchStream* bs = ctx->batch_for(stream);
   if (!bs) return fail(HRRM_ENOMEM, "batch descriptor buffers");
-  // device buffer: work counter at byte 0, image count at byte 64, descriptors
-  // from kDescOffset; uploaded from the pinned staging copy once the previous
-  // upload from it has completed
-  uint32_t* d_counter = (uint32_t*)bs->d_buf;
-  int32_t* d_hdr = (int32_t*)((char*)bs->d_buf + 64);
-  const BatchImage* d_imgs = (const BatchImage*)((char*)bs->d_buf + kDescOffset);
+  // uploaded from the pinned staging copy once the previous upload from it
+  // has completed
+  char* base = (char*)bs->d_buf;
+  uint32_t* d_counter[2] = {(uint32_t*)base, (uint32_t*)(base + 32)};
+  int32_t* d_hdr[2] = {(int32_t*)(base + 64), (int32_t*)(base + 68)};
+  const BatchImage* d_imgs[2] = {(const BatchImage*)(base + kDescOffset),
+                                 (const BatchImage*)(base + kDescOffset + kClassBytes)};
   if (bs->pending) {
     e = hipEventSynchronize(bs->staged);
     if (e != hipSuccess) return fail_hip(e, "batch staging wait");
     bs->pending = false;
   }
-  const int32_t n = (int32_t)descs.size();
+  const int32_t n[2] = {(int32_t)light.size(), (int32_t)descs.size()};
   char* stage = (char*)bs->h_stage;
-  std::memcpy(stage + 64, &n, sizeof n);
-  std::memcpy(stage + kDescOffset, descs.data(), sizeof(BatchImage) * descs.size());
-  e = hipMemcpyAsync((char*)bs->d_buf + 64, stage + 64,
-                     kDescOffset - 64 + sizeof(BatchImage) * descs.size(), hipMemcpyHostToDevice,
-                     stream);
+  std::memcpy(stage + 64, n, sizeof n);
+  std::memcpy(stage + kDescOffset, light.data(), sizeof(BatchImage) * light.size());
+  std::memcpy(stage + kDescOffset + kClassBytes, descs.data(), sizeof(BatchImage) * descs.size());
+  e = hipMemcpyAsync(base + 64, stage + 64, kDescOffset - 64 + sizeof(BatchImage) * light.size(),
+                     hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && !descs.empty())
+    e = hipMemcpyAsync(base + kDescOffset + kClassBytes, stage + kDescOffset + kClassBytes,
+                       sizeof(BatchImage) * descs.size(), hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return fail_hip(e, "batch descriptor upload");
   e = hipEventRecord(bs->staged, stream);
   if (e != hipSuccess) return fail_hip(e, "batch staging event");
   bs->pending = true;
-  const int grid = batched_grid(ctx->device);
+  const size_t lds[2] = {kBatchLightLds, kBatchLds};
+  const int grid[2] = {batched_grid(ctx->device, true), batched_grid(ctx->device, false)};
+  // both launches run every time (an empty class ends at once), so the
+  // captured graph fits every batch
+  auto launch_both = [&]() -> hipError_t {
+    for (int c = 0; c < 2; ++c) {
+      hipError_t le = launch_batched(d_imgs[c], d_hdr[c], d_counter[c], grid[c], lds[c], c == 0,
+                                     stream);
+      if (le != hipSuccess) return le;
+    }
+    return hipSuccess;
+  };
+  auto prepare_both = [&]() -> hipError_t {
+    hipError_t pe = launch_batched_prepare(lds[0], true);
+    return pe != hipSuccess ? pe : launch_batched_prepare(lds[1], false);
+  };
   if (!use_graph || stream == nullptr) {
-    e = launch_batched_prepare(kBatchLds);
+    e = prepare_both();
     if (e != hipSuccess) return fail_hip(e, "batched kernel attribute");
-    e = launch_batched(d_imgs, d_hdr, d_counter, grid, kBatchLds, stream);
+    e = launch_both();
     if (e != hipSuccess) return fail_hip(e, "batched launch");
     return HRRM_OK;
   }
   if (!bs->exec) {
-    // configure the kernel once outside capture, then capture the launch pair
-    e = launch_batched_prepare(kBatchLds);
+    // configure the kernels once outside capture, then capture the launches
+    e = prepare_both();
     if (e != hipSuccess) return fail_hip(e, "batched kernel attribute");
     e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return fail_hip(e, "hipStreamBeginCapture");
-    hipError_t le = launch_batched(d_imgs, d_hdr, d_counter, grid, kBatchLds, stream);
+    hipError_t le = launch_both();
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(stream, &g);
     if (le != hipSuccess) return fail_hip(le, "batched launch (capture)");

@@ -19,7 +19,7 @@ struct TunedEntry {
 // the captured graph of the launch.
 struct BatchStream {
   hipStream_t stream;
-  void* d_buf;        // header (image count at byte 64) + descriptors at byte 256
+  void* d_buf;        // work counters, image counts, light and heavy descriptor regions
   void* h_stage;      // pinned staging copy of d_buf's upload
   hipEvent_t staged;  // recorded after the upload; the staging copy is reused after it
   bool pending;

@@ -116,9 +116,11 @@ size_t tiered_topo_bytes(int nslots);
 // Persistent batched launch (zeroes *d_counter first, then runs `grid`
 // workgroups over all tiles of the images in d_imgs; d_hdr[0] = image count).
 // launch_batched_prepare sets the kernel's LDS limit; call it before capture.
-hipError_t launch_batched_prepare(size_t lds);
+// light = the build without matrix-core counts (images with max_groups 0),
+// four workgroups per CU.
+hipError_t launch_batched_prepare(size_t lds, bool light);
 hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32_t* d_counter,
-                          int grid, size_t lds, hipStream_t stream);
+                          int grid, size_t lds, bool light, hipStream_t stream);
 
 // Adaptive topology pre-pass (Sec. III-C).  Builds `topo` (2^bits - 1 nodes)
 // from the input's global histogram mixed 1:1 with the histogram of its

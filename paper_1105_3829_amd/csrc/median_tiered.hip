@@ -1165,10 +1165,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
 // is cut into 8 contiguous chunks with a counter each; workgroups start on the
 // chunk of their XCD (workgroups are dealt to XCDs round-robin) so that tiles
 // sharing halo rows stay in one XCD's L2, and move on to the other chunks when
-// theirs is exhausted.
-__global__ __launch_bounds__(kBlock) void k_median_batched(const BatchImage* __restrict__ imgs,
-                                                           const int32_t* __restrict__ hdr,
-                                                           uint32_t* __restrict__ counter) {
+// theirs is exhausted.  LIGHT = true builds the kernel without the
+// matrix-core counts, for four workgroups per CU (images whose tiles count no
+// subtree wave-wide); LIGHT = false serves every image with two per CU.
+template <bool LIGHT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LIGHT ? 4 : 1))) void
+k_median_batched(const BatchImage* __restrict__ imgs, const int32_t* __restrict__ hdr,
+                 uint32_t* __restrict__ counter) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ int s_tile;
   const int n = hdr[0];
@@ -1201,9 +1204,9 @@ __global__ __launch_bounds__(kBlock) void k_median_batched(const BatchImage* __r
       const int64_t local = t - (imgs[lo].tile_end - (int64_t)args.strips * args.segs);
       const int strip = (int)(local % args.strips), seg = (int)(local / args.strips);
       if (bytes == 1)
-        tile_body<uint8_t, false, false>(args, lds, strip, seg, 0);
+        tile_body<uint8_t, false, false, !LIGHT>(args, lds, strip, seg, 0);
       else
-        tile_body<uint16_t, false, false>(args, lds, strip, seg, 0);
+        tile_body<uint16_t, false, false, !LIGHT>(args, lds, strip, seg, 0);
       __syncthreads();  // LDS is reused by the next tile
     }
   }
@@ -1235,15 +1238,21 @@ size_t align16_host(size_t b) { return (b + 15) & ~(size_t)15; }
 
 }  // namespace
 
-hipError_t launch_batched_prepare(size_t lds) {
-  return ensure_dynamic_lds((const void*)k_median_batched, lds);
+hipError_t launch_batched_prepare(size_t lds, bool light) {
+  return ensure_dynamic_lds(light ? (const void*)k_median_batched<true>
+                                  : (const void*)k_median_batched<false>,
+                            lds);
 }
 
 hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32_t* d_counter,
-                          int grid, size_t lds, hipStream_t stream) {
+                          int grid, size_t lds, bool light, hipStream_t stream) {
   hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, d_counter);
-  hipLaunchKernelGGL(k_median_batched, dim3(grid), dim3(kBlock), lds, stream, d_imgs, d_hdr,
-                     d_counter);
+  if (light)
+    hipLaunchKernelGGL(k_median_batched<true>, dim3(grid), dim3(kBlock), lds, stream, d_imgs,
+                       d_hdr, d_counter);
+  else
+    hipLaunchKernelGGL(k_median_batched<false>, dim3(grid), dim3(kBlock), lds, stream, d_imgs,
+                       d_hdr, d_counter);
   return hipGetLastError();
 }
 
