@@ -99,7 +99,15 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
       t.max_groups = r <= 7 ? 0 : r <= 15 ? 1 : r <= 31 ? 4 : 64;
     else
       t.max_groups = r <= 8 ? 0 : 64;
-    if (bytes == 2) {
+    if (bytes == 2 && adaptive && r >= 10) {
+      // adaptive 16-bit trees spread a row's medians over many more deep
+      // subtrees than the uniform tree (narrow weight-balanced splits), so
+      // from r = 10 they take the whole LDS for slots: C1 r = 15 22.6 ->
+      // 10.9 ms, r = 100 142 -> 57 ms
+      t.lds_budget = kLdsLimit;
+      t.max_groups = r <= 31 ? 1 : 64;
+      rows = r <= 31 ? 48 : 16;
+    } else if (bytes == 2) {
       if (r >= 64) {
         t.lds_budget = kLdsLimit;
         rows = 128;
