@@ -86,15 +86,16 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     // Measured on MI355X (4096^2 16-bit and 8192^2 8-bit images, r = 1..127):
     // counting a tier for all 64 pixels of a wave at once (matrix cores, or
     // prefix sums past 127-value columns) pays off for more distinct subtrees
-    // per wave the wider the window; narrow windows sum per lane.  8-bit
-    // uniform trees take tall segments at every radius (two waves of tiles on
-    // an 8192^2 image).  16-bit windows run two workgroups per
-    // CU with short segments up to r = 63; from r = 64 smooth images need
-    // more slots than 80 KB holds (the churn grows with the segment) and run
-    // one workgroup per CU with the whole 160 KB and tall segments (4x faster
-    // at r = 100).  Images whose medians change fast along rows (edges) would
-    // rather keep two workgroups per CU there (1.6x); the autotuner picks
-    // per workload.
+    // per wave the wider the window; narrow windows sum per lane.  Small
+    // 16-bit windows count their deeper tiers raw and run six workgroups per
+    // CU; 8-bit trees run three or four per CU on fewer slots (smooth images
+    // need few); other 16-bit windows run two per CU with short segments up
+    // to r = 63; from r = 64 smooth images need more slots than 80 KB holds
+    // (the churn grows with the segment) and run one workgroup per CU with
+    // the whole 160 KB and tall segments (4x faster at r = 100).  Images
+    // whose medians change fast along rows (edges, noise) would rather keep
+    // more workgroups per CU there, or more slots for 8-bit trees; the
+    // autotuner picks per workload.
     if (bytes == 2)
       t.max_groups = r <= 7 ? 0 : r <= 15 ? 1 : r <= 31 ? 4 : 64;
     else
