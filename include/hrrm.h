@@ -190,9 +190,14 @@ int32_t hrrm_batch_capacity(void);
  *   tiered_u8  : 1 = 8-bit data uses tiered storage (the default), 0 = dense
  *   raw_window : windows of at most this many values ((2r+1)^D) count the
  *                deeper tiers of the tree directly from the window's values
- *                instead of holding them in slots */
+ *                instead of holding them in slots
+ *   wave_slots : 1 = (uniform 2-D trees) the workgroup shares only the first
+ *                tier's slot; each wave holds its own slots of deeper subtrees
+ *                for the 64 + 2r + 1 columns its windows cover (nslots then
+ *                caps the slots per wave); 0 = every slot shared */
 typedef struct {
   int32_t seg_rows, nslots, min_group, max_groups, lds_budget, tiered_u8, raw_window;
+  int32_t wave_slots;
 } hrrm_tile_config;
 
 /* Set (cfg != NULL) or clear (cfg == NULL) the context's tile configuration

@@ -269,7 +269,20 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;
   if (grid > 0x7fffffff) return fail(HRRM_EUNSUPPORTED, "image too large for one launch");
 
-  if (tiered) {
+  a.wslots = 0;
+  a.wpitch = 0;
+  if (tiered && t.wave_slots && !adaptive && dims == 2) {
+    // wave-private slots: slot 0 shared, the rest of the budget split into
+    // per-wave slots of 64 + 2r + 1 columns
+    a.nslots = 1;
+    a.wpitch = (64 + 2 * r + 1 + 3) & ~3;
+    const size_t budget = (size_t)std::min(std::max(t.lds_budget, 16 * 1024), kLdsLimit);
+    const size_t base = wps_lds_bytes(r, a.cp, 0, a.wpitch);
+    const size_t per = (size_t)kWaves * a.wpitch * 16;
+    int ws = budget > base ? (int)((budget - base) / per) : 0;
+    if (t.nslots > 0) ws = std::min(ws, t.nslots);
+    a.wslots = std::max(1, std::min(ws, 64));
+  } else if (tiered) {
     const size_t meta = median_lds_bytes(bytes, adaptive, true, a.ncols, a.cp, 0);
     // one 16-byte tier vector per column, plus (adaptive) the subtree's topology
     const size_t slot_bytes = (size_t)a.cp * 16 + (adaptive ? tiered_topo_bytes(1) : 0);
@@ -283,7 +296,9 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   } else {
     a.nslots = 1;
   }
-  const size_t lds = median_lds_bytes(bytes, adaptive, tiered, a.ncols, a.cp, a.nslots);
+  const size_t lds = a.wslots > 0 ? wps_lds_bytes(r, a.cp, a.wslots, a.wpitch)
+                                  : median_lds_bytes(bytes, adaptive, tiered, a.ncols, a.cp,
+                                                     a.nslots);
   if (lds > (size_t)kLdsLimit)
     return fail(HRRM_EUNSUPPORTED, "radius %d needs %zu bytes of LDS per workgroup", r, lds);
 
@@ -466,7 +481,7 @@ static bool tile_ok(const hrrm_tile_config* c) {
   return c->seg_rows >= 1 && c->nslots >= 0 && c->nslots <= kMaxSlots && c->min_group >= 1 &&
          c->min_group <= 65 && c->max_groups >= 0 && c->lds_budget >= 16 * 1024 &&
          c->lds_budget <= kLdsLimit && (c->tiered_u8 == 0 || c->tiered_u8 == 1) &&
-         c->raw_window >= 0;
+         c->raw_window >= 0 && (c->wave_slots == 0 || c->wave_slots == 1);
 }
 
 int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
@@ -487,7 +502,7 @@ int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
   if (cfg) {
     TunedEntry e{bytes, dims, r, ad, TileConfig{cfg->seg_rows, cfg->nslots, cfg->min_group,
                                                 cfg->max_groups, cfg->lds_budget, cfg->tiered_u8,
-                                                cfg->raw_window},
+                                                cfg->raw_window, cfg->wave_slots},
                  0.0};
     v.push_back(e);
   }
@@ -505,7 +520,7 @@ int hrrm_get_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
   const TileConfig t = c->tile_for(dtype == HRRM_U8 ? 1 : 2, dims, r, variant == HRRM_ADAPTIVE,
                                    width, height, dims == 3 ? depth : 1);
   *out = hrrm_tile_config{t.seg_rows, t.nslots, t.min_group, t.max_groups, t.lds_budget,
-                          t.tiered_u8, t.raw_window};
+                          t.tiered_u8, t.raw_window, t.wave_slots};
   return HRRM_OK;
 }
 

@@ -69,6 +69,9 @@ struct MedianArgs {
   int32_t max_groups; // cooperative groups per level before falling back to direct sums
   int32_t raw_window; // windows of at most this many values count a missing subtree raw
   int32_t mfma;       // 1: window counts on the matrix cores (column counts <= 127)
+  int32_t wslots;     // > 0: slots per wave of wave-private deeper subtrees (uniform 2-D)
+  int32_t wpitch;     // columns per wave-private slot (>= 64 + 2r + 1)
+  int32_t pad1;
   const TopoNode* topo;  // adaptive topology (device), else null
 };
 
@@ -90,6 +93,7 @@ struct TileConfig {
   int32_t lds_budget; // bytes of LDS one workgroup may use
   int32_t tiered_u8;  // 1 = tiered storage for u8 as well
   int32_t raw_window; // windows of at most this many values count deeper tiers raw
+  int32_t wave_slots; // 1 = deeper subtrees in wave-private slots (uniform 2-D)
 };
 
 // Launch the fused median kernel.  dims = 2 or 3; full = update every node of
@@ -111,6 +115,9 @@ size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp
 // `bytes` (1 or 2); adaptive trees add tiered_topo_bytes(nslots) for the held
 // subtrees' topology.
 size_t tiered_meta_bytes(int r, int bytes);
+// LDS bytes of a launch with wave-private slots: slot 0 (cp columns), the
+// tier state, and per wave its scratch plus `wslots` slots of `wpitch` columns.
+size_t wps_lds_bytes(int r, int cp, int wslots, int wpitch);
 size_t tiered_topo_bytes(int nslots);
 
 // Persistent batched launch (zeroes *d_counter first, then runs `grid`

@@ -332,7 +332,9 @@ size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp
 
 hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive, bool tiered,
                          bool full, hipStream_t stream) {
-  const size_t lds = median_lds_bytes(bytes, adaptive, tiered, a.ncols, a.cp, a.nslots);
+  const size_t lds = a.wslots > 0 ? wps_lds_bytes(a.r, a.cp, a.wslots, a.wpitch)
+                                  : median_lds_bytes(bytes, adaptive, tiered, a.ncols, a.cp,
+                                                     a.nslots);
   if (tiered) return launch_median_tiered(a, bytes, dims, adaptive, lds, stream);
   if (bytes != 1) return hipErrorInvalidValue;  // dense storage holds 8-bit trees only
   if (full) {

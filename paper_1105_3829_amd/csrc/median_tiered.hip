@@ -318,7 +318,7 @@ __device__ __forceinline__ void band_init(Band& bd, int span, int lane) {
 // all 64 lanes load, consecutive 8-byte words (no bank conflicts).  All 64
 // lanes must call it.
 __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots, size_t cp16,
-                                           int cp, int s, uint64_t m, int wbase, int lane,
+                                           int cmax, int s, uint64_t m, int wbase, int lane,
                                            uint8_t* stage) {
   const int g = lane >> 4, t = lane & 15;
   const uint8_t* sb = slots + (size_t)s * cp16;
@@ -331,7 +331,7 @@ __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots,
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         int c = cb + 64 * ks + 32 * h + 8 * g + (t >> 1);
-        c = c < cp - 1 ? c : cp - 1;  // past the strip: band weight 0
+        c = c < cmax ? c : cmax;  // past the slot's columns: band weight 0
         const v2i_t rr = __builtin_amdgcn_ds_read_tr8_b64_v2i32(
             (v2i_t __attribute__((address_space(3)))*)(sb + (size_t)c * 16 + 8 * (t & 1)));
         a[2 * h] = rr.x;
@@ -388,28 +388,62 @@ __device__ __forceinline__ void direct_counts(uint32_t (&W)[8], const uint8_t* s
 // window values (loads coalesced across lanes), into the wave's scratch area.
 // The caller then sums them per lane like a held slot.  Nothing is kept for
 // later rows.
-template <typename T, bool ADAPT, bool D3>
+template <typename T, bool ADAPT, bool D3, int NB = kRebRows, typename TS>
 __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict__ src,
-                                              const MedianArgs& a, const TierState<T>* ts,
+                                              const MedianArgs& a, const TS* ts,
                                               const TopoNode* topo, int64_t x0w, int64_t y,
                                               int64_t z, int lane, int span, int node, int rlo,
                                               int rhi, int rdep) {
   constexpr int bits = 8 * sizeof(T);
   const int r = a.r, zr = D3 ? r : 0, stop = a.stop;
   const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+  if constexpr (NB <= 1) {  // one row at a time: fewest registers
+    for (int c = lane; c <= 64 + span - 1; c += 64) {
+      const int64_t cx = clampi(x0w - r - 1 + c, a.w - 1);
+      uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+      for (int dz = -zr; dz <= zr; ++dz) {
+        const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+#pragma unroll 4
+        for (int j = -r; j <= r; ++j) {
+          const int v = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
+          if (v >= rlo && v <= rhi) {
+            if constexpr (ADAPT)
+              acc = add4(acc, amask(topo, node, rdep, stop, v));
+            else
+              acc = add4(acc, and4(ts->lut[nib(v, rdep, bits)], lim));
+          }
+        }
+      }
+      *(uint4*)(scr + (size_t)c * 16) = acc;
+    }
+    return;
+  }
+  // the (2zr + 1) x span window rows of each column, slice-major, NB loaded
+  // before any is used (their latencies overlap)
+  const int nrows = (2 * zr + 1) * span;
   for (int c = lane; c <= 64 + span - 1; c += 64) {
     const int64_t cx = clampi(x0w - r - 1 + c, a.w - 1);
     uint4 acc = make_uint4(0u, 0u, 0u, 0u);
-    for (int dz = -zr; dz <= zr; ++dz) {
-      const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
-#pragma unroll 4
-      for (int j = -r; j <= r; ++j) {
-        const int v = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
-        if (v >= rlo && v <= rhi) {
+    int dz = -zr, j = -r;
+    for (int q0 = 0; q0 < nrows; q0 += NB) {
+      int v[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        // rows past the window are clamped into the image, loaded and skipped
+        const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+        v[k] = src[zz * a.sss + clampi(y + j, a.h - 1) * a.srs + cx];
+        if (++j > r) {
+          j = -r;
+          ++dz;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        if (q0 + k < nrows && v[k] >= rlo && v[k] <= rhi) {
           if constexpr (ADAPT)
-            acc = add4(acc, amask(topo, node, rdep, stop, v));
+            acc = add4(acc, amask(topo, node, rdep, stop, v[k]));
           else
-            acc = add4(acc, and4(ts->lut[nib(v, rdep, bits)], lim));
+            acc = add4(acc, and4(ts->lut[nib(v[k], rdep, bits)], lim));
         }
       }
     }
@@ -419,9 +453,9 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
 
 // Per-lane counts of a tier subtree straight from the raw window values (for
 // small windows this is cheaper than building the subtree's column vectors).
-template <typename T, bool ADAPT, bool D3>
+template <typename T, bool ADAPT, bool D3, typename TS>
 __device__ __forceinline__ void raw_counts(uint32_t (&W)[8], const T* __restrict__ src,
-                                           const MedianArgs& a, const TierState<T>* ts,
+                                           const MedianArgs& a, const TS* ts,
                                            const TopoNode* topo, int64_t x, int64_t y, int64_t z,
                                            int node, int rlo, int rhi, int rdep) {
   constexpr int bits = 8 * sizeof(T);
@@ -604,7 +638,11 @@ __device__ void assign_slots(TS* ts, int nmiss, int stamp, int nslots, TopoNode*
 // of the workgroup (slots, tier state, per-wave scratch).  MF = false leaves
 // the matrix-core counts (and the 48 registers of their band) out; such
 // builds serve only launches that count no subtree wave-wide (max_groups 0).
-template <typename T, bool ADAPT, bool D3, bool MF = true>
+// WPS = true (uniform 2-D trees): the workgroup shares only slot 0 (tier 1);
+// each wave holds its own a.wslots slots of deeper subtrees, for just the
+// 64 + 2r + 1 columns its windows cover, and finds, builds, evicts and updates
+// them by itself, so tier transitions need no workgroup barrier.
+template <typename T, bool ADAPT, bool D3, bool MF = true, bool WPS = false>
 __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int strip, int seg,
                                           int64_t z) {
   const T* __restrict__ src = (const T*)a.src;
@@ -621,12 +659,22 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
   const int64_t yb = (int64_t)seg * a.seg_rows;
   const int64_t ye = yb + a.seg_rows < a.h ? yb + a.seg_rows : a.h;
 
+  static_assert(!WPS || (!ADAPT && !D3), "wave-private slots serve uniform 2-D trees");
   uint8_t* slots = lds;
-  using TS = TierState<T>;
+  using TS = TierStateT<(sizeof(T) == 1 || WPS) ? 16 : kSmap>;
   TS* ts = (TS*)(lds + align16((size_t)a.nslots * cp16));
-  // per-wave scratch of (64 + 2r + 1) column vectors for subtrees no slot holds
-  uint8_t* scr = lds + align16((size_t)a.nslots * cp16) + align16(sizeof(TS)) +
-                 (size_t)wv * wave_scratch_bytes(r);
+  // per-wave scratch of (64 + 2r + 1) column vectors for subtrees no slot
+  // holds (WPS: followed by the wave's own slots)
+  const size_t wpitch16 = (size_t)a.wpitch * 16;
+  const size_t warea = wave_scratch_bytes(r) + (WPS ? (size_t)a.wslots * wpitch16 : 0);
+  uint8_t* scr = lds + align16((size_t)a.nslots * cp16) + align16(sizeof(TS)) + (size_t)wv * warea;
+  // WPS: the wave's slots, addressed by tile column (the wave's columns
+  // 64 wv .. 64 wv + 64 + 2r start at its first slot)
+  uint8_t* wslots = scr + wave_scratch_bytes(r) - (size_t)wv * 64 * 16;
+  const int wcmax = wv * 64 + 64 + 2 * r;  // last tile column of the wave's slots
+  // lane s < a.wslots describes wave slot s: interval start, depth (-1: empty)
+  // and the last row that used it
+  int wlo = -1, wdep = -1, wst = -1;
   // adaptive: topology of each held subtree (16 entries per slot) after the scratch
   TopoNode* stopo = (TopoNode*)(lds + align16((size_t)a.nslots * cp16) +
                                 align16(sizeof(TS)) + (size_t)kWaves * wave_scratch_bytes(r));
@@ -766,6 +814,12 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
 
     for (int round = 0; round <= maxrounds; ++round) {
       const bool act = !done;
+      // the slots this round's counts read: tier 1 and shared slots, or
+      // (WPS, deeper tiers) the wave's own
+      const bool own = WPS && round > 0;
+      const uint8_t* cslots = own ? wslots : slots;
+      const size_t ccp16 = own ? wpitch16 : cp16;
+      const int cmax = own ? wcmax : a.cp - 1;
       const uint64_t pend = ballot(act && slot >= 0);
       uint32_t W[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
       if (pend) {
@@ -778,7 +832,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
             const int s = readlane(slot, __builtin_ctzll(t));
             const uint64_t m = ballot(slot == s) & t;
             t &= ~m;
-            mfma_group(band, slots, cp16, a.cp, s, m, wv * 64, lane, scr);
+            mfma_group(band, cslots, ccp16, cmax, s, m, wv * 64, lane, scr);
           }
           wave_sync_lds();
           if ((pend >> lane) & 1) {
@@ -795,10 +849,10 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
             const int s = readlane(slot, __builtin_ctzll(t));
             const uint64_t m = ballot(slot == s) & t;
             t &= ~m;
-            coop_counts(W, slots, cp16, s, (m >> lane) & 1, lx, span, lane, wv * 64);
+            coop_counts(W, cslots, ccp16, s, (m >> lane) & 1, lx, span, lane, wv * 64);
           }
         } else if (act && slot >= 0) {
-          direct_counts(W, slots, cp16, slot, lx, span, batch);
+          direct_counts(W, cslots, ccp16, slot, lx, span, batch);
         }
       }
       // Pixels whose subtree no slot holds: small windows, and waves whose
@@ -828,8 +882,11 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
         const int kdep = readlane(depth, leader), knode = readlane(node, leader);
         const uint64_t m = ballot(act && slot < 0 && lo == klo && depth == kdep) & fb;
         fb &= ~m;
-        scratch_build<T, ADAPT, D3>(scr, src, a, ts, topo, x0 + wv * 64, y, z, lane, span, knode,
-                                    klo, khi, kdep);
+        // (builds without the matrix cores keep to few registers: they run
+        // many workgroups per CU; adaptive volumes walk the topology per
+        // value, where batched loads measured slower)
+        scratch_build<T, ADAPT, D3, (MF && !(ADAPT && D3) ? kRebRows : 1)>(
+            scr, src, a, ts, topo, x0 + wv * 64, y, z, lane, span, knode, klo, khi, kdep);
         wave_sync_lds();
         if ((m >> lane) & 1) direct_counts(W, scr - (size_t)wv * 64 * 16, 0, 0, lx, span, batch);
         wave_sync_lds();
@@ -907,6 +964,60 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
       if (raw_only) {  // deeper tiers are all counted raw: no shared state, no barrier
         if (exited) slot = -1;
         if (ballot(exited) == 0) break;
+        continue;
+      }
+      if constexpr (WPS) {
+        // Wave-private slots: per subtree the exited lanes enter (lanes
+        // grouped by interval start and depth), the wave finds it among its
+        // own slots or builds it into the least recently used slot no lane
+        // used in this row - when a group of kSlotLanes lanes shares it, or
+        // the wave wants at most kMissGroups subtrees; other lanes are counted
+        // wave-locally in the next round.
+        const uint64_t ex = ballot(exited);
+        if (ex == 0) break;
+        int ng = 0;
+        for (uint64_t u = ex; u && ng <= kMissGroups; ++ng) {
+          const int l = __builtin_ctzll(u);
+          u &= ~ballot(lo == readlane(lo, l) && depth == readlane(depth, l));
+        }
+        const int min_lanes = ng <= kMissGroups ? 1 : kSlotLanes;
+        int newslot = -1;
+        for (uint64_t u = ex; u;) {
+          const int l = __builtin_ctzll(u);
+          const int klo = readlane(lo, l), kdep = readlane(depth, l);
+          const uint64_t m = ballot(exited && lo == klo && depth == kdep) & u;
+          u &= ~m;
+          // lane s holds slot s: one ballot finds the subtree among them
+          const uint64_t hit = ballot(lane < a.wslots && wdep == kdep && wlo == klo);
+          int found = hit ? (int)__builtin_ctzll(hit) : -1, victim = -1;
+          if (found < 0 && __builtin_popcountll(m) >= min_lanes) {
+            int best = 0x7fffffff;
+            for (int s = 0; s < a.wslots; ++s) {
+              const int sst = readlane(wst, s);
+              if (sst != (int)y && sst < best) {
+                best = sst;
+                victim = s;
+              }
+            }
+          }
+          if (victim >= 0) {
+            scratch_build<T, false, false>(wslots + (size_t)victim * wpitch16 +
+                                               (size_t)wv * 64 * 16,
+                                           src, a, ts, topo, x0 + wv * 64, y, z, lane, span, 0,
+                                           klo, klo + (1 << (bits - kdep)) - 1, kdep);
+            wave_sync_lds();
+            if (lane == victim) {
+              wlo = klo;
+              wdep = kdep;
+            }
+            found = victim;
+          }
+          if (found >= 0) {
+            if (lane == found) wst = (int)y;
+            if ((m >> lane) & 1) newslot = found;
+          }
+        }
+        if (exited) slot = newslot;  // -1: counted wave-locally
         continue;
       }
       const int key = exited ? (ADAPT ? node
@@ -1070,6 +1181,42 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
             }
           }
         }
+      } else if (WPS && yo != yi) {
+        // wave-private slots: tier 1 in slot 0 for columns tid and tid + 256;
+        // then each wave brings its own slots up to date for its columns
+        // 64 wv + j, j = lane, lane + 64, ... up to 64 + 2r
+        const uint4 lim1 = level_mask(stop - pl < kTierLevels ? stop - pl : kTierLevels);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int lc = tid + k * kBlock;
+          if (lc < ncols && pl < stop)
+            pair_update(lc, 0, 0, and4(ts->lut[nib(pre_o[k], pl, bits)], lim1),
+                        and4(ts->lut[nib(pre_i[k], pl, bits)], lim1));
+        }
+        const uint64_t held = ballot(lane < a.wslots && wdep >= 0);
+        for (int k = 0; tid + 64 * k <= wcmax; ++k) {
+          const int lc = tid + 64 * k;  // tile column 64 wv + lane + 64 k
+          int vo = pre_o[0], vi = pre_i[0];
+          if (k > 0) {
+            const int64_t cx = clampi(x0 - r - 1 + lc, a.w - 1);
+            vo = src[z * a.sss + yo * a.srs + cx];
+            vi = src[z * a.sss + yi * a.srs + cx];
+          }
+          for (uint64_t hs = held; hs; hs &= hs - 1) {
+            const int s = __builtin_ctzll(hs);
+            const int sdep = readlane(wdep, s);
+            const int slo = readlane(wlo, s), shi = slo + (1 << (bits - sdep)) - 1;
+            const bool io = vo >= slo && vo <= shi, ii = vi >= slo && vi <= shi;
+            if (io || ii) {
+              const uint4 lim = level_mask(stop - sdep < kTierLevels ? stop - sdep : kTierLevels);
+              uint4& cv = *(uint4*)(wslots + (size_t)s * wpitch16 + (size_t)lc * 16);
+              uint4 c = cv;
+              if (io) c = sub4(c, and4(ts->lut[nib(vo, sdep, bits)], lim));
+              if (ii) c = add4(c, and4(ts->lut[nib(vi, sdep, bits)], lim));
+              cv = c;
+            }
+          }
+        }
       } else if (!ADAPT && !D3 && yo != yi) {
         // uniform 2-D: the thread owns columns tid and tid + 256 (if any); per
         // tier the slots and masks of both columns' leaving and entering values
@@ -1149,13 +1296,13 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
 // workgroups of kLdsQuarter / kLdsSixth bytes share one; WPE = 1 leaves the
 // register allocation free (workgroups with larger budgets run at most two
 // per CU anyway).
-template <typename T, bool ADAPT, bool D3, int WPE>
+template <typename T, bool ADAPT, bool D3, int WPE, bool WPS = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) void k_median_tiered(
     MedianArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int rest = bid / a.strips;
-  tile_body<T, ADAPT, D3, (WPE <= 3)>(a, lds, bid % a.strips, rest % a.segs, rest / a.segs);
+  tile_body<T, ADAPT, D3, (WPE <= 3), WPS>(a, lds, bid % a.strips, rest % a.segs, rest / a.segs);
 }
 
 // Persistent batched launch: every workgroup repeatedly takes the next tile
@@ -1219,6 +1366,17 @@ __global__ void k_zero_counter(uint32_t* counter) {
 template <typename T, bool ADAPT, bool D3>
 hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
   auto kern = k_median_tiered<T, ADAPT, D3, 1>;
+  if constexpr (!ADAPT && !D3) {
+    if (a.wslots > 0) {
+      kern = lds <= (size_t)kLdsThird ? k_median_tiered<T, false, false, 3, true>
+                                      : k_median_tiered<T, false, false, 1, true>;
+      hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
+      if (e != hipSuccess) return e;
+      const int64_t grid = (int64_t)a.strips * a.segs * a.d;
+      hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(kBlock), lds, stream, a);
+      return hipGetLastError();
+    }
+  }
   if constexpr (!ADAPT) {
     if (lds <= (size_t)kLdsSixth && a.max_groups == 0)
       kern = k_median_tiered<T, ADAPT, D3, 6>;
@@ -1259,6 +1417,11 @@ hipError_t launch_batched(const BatchImage* d_imgs, const int32_t* d_hdr, uint32
 size_t tiered_meta_bytes(int r, int bytes) {
   const size_t st = bytes == 1 ? sizeof(TierState<uint8_t>) : sizeof(TierState<uint16_t>);
   return align16_host(st) + (size_t)kWaves * wave_scratch_bytes(r);
+}
+
+size_t wps_lds_bytes(int r, int cp, int wslots, int wpitch) {
+  return align16_host((size_t)cp * 16) + align16_host(sizeof(TierStateT<16>)) +
+         (size_t)kWaves * (wave_scratch_bytes(r) + (size_t)wslots * wpitch * 16);
 }
 
 size_t tiered_topo_bytes(int nslots) { return (size_t)nslots * 16 * sizeof(TopoNode); }

@@ -82,10 +82,10 @@ int save_tuning(const Context* c, const char* path) {
     fprintf(f,
             " {\"bytes\": %d, \"dims\": %d, \"r\": %d, \"adaptive\": %d, \"seg_rows\": %d, "
             "\"nslots\": %d, \"min_group\": %d, \"max_groups\": %d, \"lds_budget\": %d, "
-            "\"tiered_u8\": %d, \"raw_window\": %d, \"ms\": %.5f}%s\n",
+            "\"tiered_u8\": %d, \"raw_window\": %d, \"wave_slots\": %d, \"ms\": %.5f}%s\n",
             e.bytes, e.dims, e.r, e.adaptive, e.cfg.seg_rows, e.cfg.nslots, e.cfg.min_group,
-            e.cfg.max_groups, e.cfg.lds_budget, e.cfg.tiered_u8, e.cfg.raw_window, e.ms,
-            i + 1 < c->tuned.size() ? "," : "");
+            e.cfg.max_groups, e.cfg.lds_budget, e.cfg.tiered_u8, e.cfg.raw_window,
+            e.cfg.wave_slots, e.ms, i + 1 < c->tuned.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -106,22 +106,24 @@ int load_tuning(Context* c, const char* path) {
   char line[1024];
   std::vector<TunedEntry> got;
   while (fgets(line, sizeof line, f)) {
-    double v[12];
-    const char* names[12] = {"bytes", "dims", "r", "adaptive", "seg_rows", "nslots", "min_group",
-                             "max_groups", "lds_budget", "tiered_u8", "ms", "raw_window"};
+    double v[13];
+    const char* names[13] = {"bytes",      "dims",      "r",  "adaptive",   "seg_rows",
+                             "nslots",     "min_group", "max_groups",       "lds_budget",
+                             "tiered_u8",  "ms",        "raw_window",       "wave_slots"};
     bool ok = true;
     for (int i = 0; i < 11 && ok; ++i) ok = field(line, names[i], &v[i]);
     if (!ok) continue;
     if (!field(line, names[11], &v[11])) v[11] = 49;
+    if (!field(line, names[12], &v[12])) v[12] = 0;
     TunedEntry e{(int)v[0], (int)v[1], (int)v[2], (int)v[3],
                  TileConfig{(int32_t)v[4], (int32_t)v[5], (int32_t)v[6], (int32_t)v[7],
-                            (int32_t)v[8], (int32_t)v[9], (int32_t)v[11]},
+                            (int32_t)v[8], (int32_t)v[9], (int32_t)v[11], (int32_t)v[12]},
                  v[10]};
     const TileConfig& t = e.cfg;
     if ((e.bytes != 1 && e.bytes != 2) || (e.dims != 2 && e.dims != 3) || e.r < 0 ||
         t.seg_rows < 1 || t.nslots < 0 || t.nslots > kMaxSlots || t.min_group < 1 ||
         t.max_groups < 0 || t.lds_budget < 16 * 1024 || t.lds_budget > kLdsLimit ||
-        t.raw_window < 0)
+        t.raw_window < 0 || (t.wave_slots != 0 && t.wave_slots != 1))
       continue;
     got.push_back(e);
   }
@@ -214,12 +216,13 @@ int autotune(Context* c, const void* d_sample, int dtype, int r, int variant, in
     else axes.push_back({2, {1, 2, 4, 8}});                               // min_group
     if (bytes == 1) axes.push_back({5, {0, 1}});                          // tiered_u8
     axes.push_back({6, {0, 9, 27, 49, 81}});                              // raw_window
+    if (!adaptive) axes.push_back({7, {0, 1}});                           // wave_slots
     for (int pass = 0; pass < 2; ++pass) {
       for (auto& ax : axes) {
         for (int v : ax.second) {
           TileConfig t = cur;
-          int32_t* f[7] = {&t.seg_rows, &t.nslots, &t.min_group, &t.max_groups, &t.lds_budget,
-                           &t.tiered_u8, &t.raw_window};
+          int32_t* f[8] = {&t.seg_rows,   &t.nslots,    &t.min_group,  &t.max_groups,
+                           &t.lds_budget, &t.tiered_u8, &t.raw_window, &t.wave_slots};
           if (*f[ax.first] == v) continue;
           *f[ax.first] = v;
           if (ax.first == 5 && v == 1 && t.max_groups > 8) t.max_groups = 1;

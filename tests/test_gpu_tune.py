@@ -23,7 +23,9 @@ CONFIGS = [dict(seg_rows=1), dict(seg_rows=7), dict(seg_rows=300), dict(lds_budg
            dict(lds_budget=160 * 1024), dict(nslots=1), dict(nslots=2), dict(max_groups=0),
            dict(max_groups=64), dict(min_group=1), dict(min_group=65), dict(tiered_u8=1),
            dict(tiered_u8=1, max_groups=0), dict(tiered_u8=1, nslots=1), dict(tiered_u8=0),
-           dict(raw_window=0), dict(raw_window=100000), dict(raw_window=100000, nslots=1)]
+           dict(raw_window=0), dict(raw_window=100000), dict(raw_window=100000, nslots=1),
+           dict(wave_slots=1), dict(wave_slots=1, nslots=1), dict(wave_slots=1, max_groups=0),
+           dict(wave_slots=1, lds_budget=160 * 1024), dict(wave_slots=1, raw_window=0)]
 
 
 @pytest.mark.parametrize("kind,r", [("u8", 3), ("u16", 5), ("u16", 40), ("u8", 70)])
@@ -43,6 +45,28 @@ def test_every_tile_config_same_output(hrrm, kind, r):
             got = to_host(ctx.median2d(d, r, variant=variant))
             assert np.array_equal(got, want), (cfg, variant, first_mismatch(got, want))
             ctx.set_tile(dt, 2, r, variant, None)
+
+
+@pytest.mark.parametrize("kind,r", [("u16", 9), ("u16", 15), ("u16", 31), ("u16", 33), ("u16", 64),
+                                    ("u16", 127), ("u8", 16), ("u8", 100)])
+def test_wave_private_slots(hrrm, kind, r):
+    # deeper subtrees in per-wave slots: every wave builds, evicts and updates
+    # its own, including windows wider than 64 columns (several update passes)
+    ctx = hrrm.Context(0)
+    if kind == "u8":
+        img, dt = datagen.uniform_u8(110, 600, seed=80 + r), hrrm.U8
+    else:
+        img, dt = datagen.uniform_u16(100, 560, seed=80 + r), hrrm.U16
+    want = oracle.median2d(img, r)
+    d = to_dev(img)
+    for budget in (24 * 1024, 80 * 1024):
+        c = ctx.get_tile(dt, 2, r)
+        c.wave_slots, c.lds_budget, c.seg_rows = 1, budget, 37
+        ctx.set_tile(dt, 2, r, "plain", c)
+        announce("wave slots", kind, r, budget)
+        got = to_host(ctx.median2d(d, r))
+        assert np.array_equal(got, want), (budget, first_mismatch(got, want))
+    ctx.set_tile(dt, 2, r, "plain", None)
 
 
 def test_autotune_cache_roundtrip(hrrm, tmp_path):
