@@ -500,7 +500,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // the values of its window that fall in its interval to a private 16-bin
 // histogram of the four value bits below dep; the 15 left-node counts follow
 // from the bins.  All 64 lanes must call it; buf is the wave's scratch area.
-template <typename T, bool D3>
+template <typename T, bool D3, bool PIPE>
 __device__ __forceinline__ void raw_wave(uint32_t (&W)[8], bool need, int lo, int dep,
                                          uint8_t* buf, const T* __restrict__ src,
                                          const MedianArgs& a, int64_t x0w, int64_t y, int64_t z,
@@ -512,11 +512,54 @@ __device__ __forceinline__ void raw_wave(uint32_t (&W)[8], bool need, int lo, in
   const uint32_t width = need ? 1u << (bits - dep) : 0u;
 #pragma unroll
   for (int k = 0; k < 8; ++k) hist[k * 64 + lane] = 0;
-  for (int dz = -zr; dz <= zr; ++dz) {
-    const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
-    for (int dy = -r; dy <= r; ++dy) {
-      const T* rowp = src + zz * a.sss + clampi(y + dy, a.h - 1) * a.srs;
-      for (int c = lane; c < 64 + 2 * r; c += 64) stage[c] = rowp[clampi(x0w - r + c, a.w - 1)];
+  if constexpr (!PIPE) {  // one row at a time: fewest registers
+    for (int dz = -zr; dz <= zr; ++dz) {
+      const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+      for (int dy = -r; dy <= r; ++dy) {
+        const T* rowp = src + zz * a.sss + clampi(y + dy, a.h - 1) * a.srs;
+        for (int c = lane; c < 64 + 2 * r; c += 64) stage[c] = rowp[clampi(x0w - r + c, a.w - 1)];
+        wave_sync_lds();
+        if (need) {
+          for (int dx = 0; dx < span; ++dx) {
+            const uint32_t v = stage[lane + dx];
+            if (v - (uint32_t)lo < width) {
+              const int bn = nib((int)v, dep, bits);
+              atomicAdd(&hist[(bn >> 1) * 64 + lane], 1u << ((bn & 1) * 16));
+            }
+          }
+        }
+        wave_sync_lds();
+      }
+    }
+  } else {
+    // lane l stages columns l, l + 64, ... of each window row (64 + 2r
+    // values); the first two of the next row are loaded into registers before
+    // the current row is counted, so their latency overlaps the counting
+    const int nrows = (2 * zr + 1) * span;
+    const int nstage = 64 + 2 * r;
+    auto row_ptr = [&](int dz, int dy) -> const T* {
+      const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+      return src + zz * a.sss + clampi(y + dy, a.h - 1) * a.srs;
+    };
+    int qdz = -zr, qdy = -r;  // the current row
+    const T* rp = row_ptr(qdz, qdy);
+    T c0 = rp[clampi(x0w - r + lane, a.w - 1)];
+    T c1 = lane + 64 < nstage ? rp[clampi(x0w - r + lane + 64, a.w - 1)] : (T)0;
+    for (int q = 0; q < nrows; ++q) {
+      stage[lane] = c0;
+      if (lane + 64 < nstage) stage[lane + 64] = c1;
+      for (int c = lane + 128; c < nstage; c += 64) stage[c] = rp[clampi(x0w - r + c, a.w - 1)];
+      int ndz = qdz, ndy = qdy + 1;
+      if (ndy > r) {
+        ndy = -r;
+        ++ndz;
+      }
+      const T* np = row_ptr(ndz, ndy);  // clamped into the image past the last row
+      T n0 = (T)0, n1 = (T)0;
+      if (q + 1 < nrows) {
+        n0 = np[clampi(x0w - r + lane, a.w - 1)];
+        if (lane + 64 < nstage) n1 = np[clampi(x0w - r + lane + 64, a.w - 1)];
+      }
       wave_sync_lds();
       if (need) {
         for (int dx = 0; dx < span; ++dx) {
@@ -528,6 +571,11 @@ __device__ __forceinline__ void raw_wave(uint32_t (&W)[8], bool need, int lo, in
         }
       }
       wave_sync_lds();
+      c0 = n0;
+      c1 = n1;
+      qdz = ndz;
+      qdy = ndy;
+      rp = np;
     }
   }
   if (need) {
@@ -873,7 +921,11 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           if (act && slot < 0) raw_counts<T, ADAPT, D3>(W, src, a, ts, topo, x, y, z, node, lo, hi,
                                                         depth);
         } else {
-          raw_wave<T, D3>(W, act && slot < 0, lo, depth, scr, src, a, x0 + wv * 64, y, z, lane);
+          // (the builds without matrix-core counts, which run raw-counted
+          // windows at four or six workgroups per CU, load the next row
+          // while counting the current one)
+          raw_wave<T, D3, !MF>(W, act && slot < 0, lo, depth, scr, src, a, x0 + wv * 64, y, z,
+                               lane);
         }
       } else
       for (uint64_t fb = nos; fb;) {
