@@ -91,7 +91,9 @@ int hrrm_ctx_destroy(hrrm_ctx ctx);
 /* Pre-size the workspaces so later calls up to these sizes allocate nothing
  * (required before capturing adaptive calls into a HIP graph: a call that
  * would have to grow a workspace while its stream is being captured fails
- * with ENOMEM).  max_pixels counts pixels (2-D) or voxels (3-D). */
+ * with ENOMEM), and raise every kernel's LDS limit on the context's device
+ * once, so later calls make no function-attribute call either.  max_pixels
+ * counts pixels (2-D) or voxels (3-D). */
 int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t max_r,
                      hrrm_variant variant);
 

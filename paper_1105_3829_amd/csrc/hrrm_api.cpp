@@ -402,6 +402,11 @@ int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t
   if (max_pixels < 0 || max_r < 0) return fail(HRRM_EINVAL, "negative size");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  // every kernel's LDS limit once, so later (captured) calls set no attribute
+  e = prime_tiered_lds();
+  if (e == hipSuccess) e = prime_dense_lds();
+  if (e == hipSuccess) e = prime_topology_lds();
+  if (e != hipSuccess) return fail_hip(e, "kernel LDS limits");
   if (variant == HRRM_ADAPTIVE)
     return c->ensure_topology(dtype == HRRM_U8 ? 1 : 2, max_pixels, nullptr);
   return HRRM_OK;

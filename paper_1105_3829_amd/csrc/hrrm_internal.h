@@ -108,6 +108,13 @@ hipError_t launch_median(const MedianArgs& a, int bytes, int dims, bool adaptive
 // launches under stream capture) make no attribute call.
 hipError_t ensure_dynamic_lds(const void* kernel, size_t bytes);
 
+// Raise the dynamic-LDS limit of every build of the tiered, batched, dense and
+// topology kernels to the most any launch can ask for, on the current device,
+// so that no later launch makes an attribute call (hrrm_ctx_reserve).
+hipError_t prime_tiered_lds();
+hipError_t prime_dense_lds();
+hipError_t prime_topology_lds();
+
 // LDS bytes a launch with these parameters needs.
 size_t median_lds_bytes(int bytes, bool adaptive, bool tiered, int ncols, int cp, int nslots);
 

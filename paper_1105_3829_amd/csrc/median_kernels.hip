@@ -317,6 +317,20 @@ hipError_t launch_dense(const MedianArgs& a, size_t lds, hipStream_t stream) {
 
 }  // namespace
 
+hipError_t prime_dense_lds() {
+  const void* ks[] = {(const void*)k_median_dense<uint8_t, false, false, false>,
+                      (const void*)k_median_dense<uint8_t, true, false, false>,
+                      (const void*)k_median_dense<uint8_t, false, true, false>,
+                      (const void*)k_median_dense<uint8_t, true, true, false>,
+                      (const void*)k_median_dense<uint8_t, false, false, true>,
+                      (const void*)k_median_dense<uint8_t, false, true, true>};
+  for (const void* k : ks) {
+    const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_median_tiered(const MedianArgs& a, int bytes, int dims, bool adaptive,
                                 size_t lds, hipStream_t stream);
 

@@ -1446,7 +1446,36 @@ hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
 
 size_t align16_host(size_t b) { return (b + 15) & ~(size_t)15; }
 
+// Raise the LDS limit of every build of the tiered kernel for one element type.
+template <typename T>
+hipError_t prime_type() {
+  const void* ks[] = {
+      (const void*)k_median_tiered<T, false, false, 1>, (const void*)k_median_tiered<T, false, false, 3>,
+      (const void*)k_median_tiered<T, false, false, 4>, (const void*)k_median_tiered<T, false, false, 6>,
+      (const void*)k_median_tiered<T, false, true, 1>,  (const void*)k_median_tiered<T, false, true, 3>,
+      (const void*)k_median_tiered<T, false, true, 4>,  (const void*)k_median_tiered<T, false, true, 6>,
+      (const void*)k_median_tiered<T, true, false, 1>,  (const void*)k_median_tiered<T, true, true, 1>,
+      (const void*)k_median_tiered<T, false, false, 1, true>,
+      (const void*)k_median_tiered<T, false, false, 3, true>};
+  for (const void* k : ks) {
+    const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 }  // namespace
+
+hipError_t prime_tiered_lds() {
+  hipError_t e = prime_type<uint8_t>();
+  if (e == hipSuccess) e = prime_type<uint16_t>();
+  // (the persistent kernel declares a few static bytes of its own)
+  if (e == hipSuccess)
+    e = ensure_dynamic_lds((const void*)k_median_batched<true>, kLdsLimit - 256);
+  if (e == hipSuccess)
+    e = ensure_dynamic_lds((const void*)k_median_batched<false>, kLdsLimit - 256);
+  return e;
+}
 
 hipError_t launch_batched_prepare(size_t lds, bool light) {
   return ensure_dynamic_lds(light ? (const void*)k_median_batched<true>

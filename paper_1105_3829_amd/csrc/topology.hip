@@ -250,6 +250,14 @@ static hipError_t build_levels(const Ws& w, int bits, TopoNode* topo, hipStream_
   return hipGetLastError();
 }
 
+hipError_t prime_topology_lds() {
+  // the 16-bit histograms: 2^16 16-bit bins
+  const size_t hlds = ((size_t)1 << 16) * 2;
+  hipError_t e = ensure_dynamic_lds((const void*)k_hist<uint16_t>, hlds);
+  if (e == hipSuccess) e = ensure_dynamic_lds((const void*)k_box<uint32_t, true>, hlds);
+  return e;
+}
+
 size_t topology_workspace_bytes(int bits, int64_t pixels) {
   const size_t nb = (size_t)1 << bits;
   return al(nb * 4) * 2 + al((nb + 1) * 8) + 2 * al(nb / 2 * sizeof(int4)) + al(16) +

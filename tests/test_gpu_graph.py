@@ -53,3 +53,47 @@ def test_captured_calls_replay_like_eager(hrrm):
         for name, o in outs.items():
             got = to_host(o)
             assert np.array_equal(got, want[name]), (rep, name, first_mismatch(got, want[name]))
+
+
+def test_capture_without_warmup_after_reserve(hrrm):
+    # reserve raises every kernel build's LDS limit, so calls captured with no
+    # eager call before them (builds for six, four and three workgroups per
+    # CU, 3-D, wave-private slots) record only launches
+    import torch
+    ctx = hrrm.Context(0)
+    img16 = to_dev(datagen.xray_u16(200, 600, seed=172))
+    img8 = to_dev(datagen.lowkey_u8(180, 520, seed=173))
+    vol = to_dev(datagen.xray_volume_u16(4, 40, 300, seed=174))
+    ctx.reserve(hrrm.U16, img16.numel(), 12, "plain")
+    c = ctx.get_tile(hrrm.U16, 2, 12)
+    c.wave_slots = 1
+    ctx.set_tile(hrrm.U16, 2, 12, "plain", c)
+    calls = [("u16 r=2", lambda o: ctx.median2d(img16, 2, out=o), img16),
+             ("u8 r=3", lambda o: ctx.median2d(img8, 3, out=o), img8),
+             ("u8 r=20", lambda o: ctx.median2d(img8, 20, out=o), img8),
+             ("u16 r=12 wave slots", lambda o: ctx.median2d(img16, 12, out=o), img16),
+             ("3-D r=1", lambda o: ctx.median3d(vol, 1, out=o), vol)]
+    outs = {name: torch.empty_like(src) for name, _, src in calls}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    announce("capture without warm-up")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        for name, fn, _ in calls:
+            fn(outs[name])
+    want = {}
+    for name, fn, src in calls:
+        o = torch.empty_like(src)
+        fn(o)
+        want[name] = to_host(o)
+    for rep in range(2):
+        for o in outs.values():
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for name, o in outs.items():
+            got = to_host(o)
+            assert np.array_equal(got, want[name]), (rep, name, first_mismatch(got, want[name]))
+    ctx.set_tile(hrrm.U16, 2, 12, "plain", None)
