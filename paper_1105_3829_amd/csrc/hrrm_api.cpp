@@ -262,8 +262,10 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   a.min_group = std::max(1, t.min_group);
   a.max_groups = std::max(0, t.max_groups);
   a.raw_window = std::max(0, t.raw_window);
-  // the matrix cores take column counts as signed bytes
-  a.mfma = (dims == 3 ? (2 * r + 1) * (2 * r + 1) : 2 * r + 1) <= 127;
+  // the matrix cores take column counts as signed bytes (volumes: shifted by
+  // -128 for counts past 127), over at most three 64-column steps
+  const int maxcol = dims == 3 ? (2 * r + 1) * (2 * r + 1) : 2 * r + 1;
+  a.mfma = maxcol <= 127 ? 1 : dims == 3 && maxcol <= 255 ? 2 : 0;
   a.topo = nullptr;
 
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;

@@ -68,7 +68,8 @@ struct MedianArgs {
   int32_t min_group;  // smallest lane group counted cooperatively
   int32_t max_groups; // cooperative groups per level before falling back to direct sums
   int32_t raw_window; // windows of at most this many values count a missing subtree raw
-  int32_t mfma;       // 1: window counts on the matrix cores (column counts <= 127)
+  int32_t mfma;       // window counts on the matrix cores: 1 (column counts <= 127), 2 (3-D,
+                      // counts <= 255 as shifted bytes); 0 = not
   int32_t wslots;     // > 0: slots per wave of wave-private deeper subtrees (uniform 2-D)
   int32_t wpitch;     // columns per wave-private slot (>= 64 + 2r + 1)
   int32_t pad1;
