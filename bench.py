@@ -41,30 +41,51 @@ def workload(name: str, r: int):
         return datagen.uniform_u8(512, 512, seed=0), "u8 512x512 uniform"
     if name == "c2":
         return datagen.lowkey_u8(8192, 8192, seed=2), "u8 8192x8192 low-key"
+    if name == "c3":
+        return (datagen.xray_volume_u16(256, 512, 512, seed=3),
+                "u16 512x512x256 X-ray-like volume with 1% impulses")
     raise SystemExit("unknown workload %s" % name)
 
 
-def lds_work_per_pixel(img, variant: str = "plain") -> tuple:
+def lds_work_per_pixel(img, variant: str = "plain", r: int = 0) -> tuple:
     """Algorithmic LDS dword-operations per output pixel of the uniform method:
     2*zbar counter updates (one removal, one insertion per column per row; an
-    update touches the levels where the value's bit is 0) plus two
-    column-counter reads (entering and leaving column) per window-tree node
-    brought up to date: the d nodes the descent visits for the on-demand
-    update, all 2^d - 1 nodes for the full update.  zbar is exact for this
-    input (from its histogram)."""
+    update touches the levels where the value's bit is 0; a volume's column
+    takes 2r + 1 of each per row step) plus two column-counter reads (entering
+    and leaving column) per window-tree node brought up to date: the d nodes
+    the descent visits for the on-demand update, all 2^d - 1 nodes for the
+    full update.  zbar is exact for this input (from its histogram)."""
     import numpy as np
     d = 8 * img.dtype.itemsize
     hist = np.bincount(img.ravel(), minlength=1 << d).astype(np.float64)
     ones = np.array([bin(v).count("1") for v in range(1 << d)], dtype=np.float64)
     zbar = d - float((hist * ones).sum() / hist.sum())
     nodes = (1 << d) - 1 if variant == "full" else d
-    return 2.0 * zbar + 2.0 * nodes, zbar, d
+    per_step = 2 * r + 1 if img.ndim == 3 else 1
+    return 2.0 * zbar * per_step + 2.0 * nodes, zbar, d
 
 
 def cpu_baseline(img, r: int, seconds_target: float = 10.0):
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    if img.ndim == 3:
+        # a slab of whole slices, clamped at the slab's own bottom slice
+        d, h, w = img.shape
+        probe = np.ascontiguousarray(img[:1])
+        t = time.perf_counter()
+        oracle.median3d(probe, r, threads=threads)
+        rate = probe.size / max(time.perf_counter() - t, 1e-6)
+        n = int(max(1, min(d, seconds_target * rate / (h * w))))
+        slab = np.ascontiguousarray(img[:n])
+        t = time.perf_counter()
+        oracle.median3d(slab, r, threads=threads)
+        dt = time.perf_counter() - t
+        return {"value": round(slab.size / dt / 1e6, 4), "unit": "Mvox/s", "cores": threads,
+                "kind": "oracle",
+                "sample": "slices 0..%d of the same volume (%d x %d x %d voxels, clamp at the "
+                          "slab's own last slice), brute-force nth_element per window, %.1f s" % (
+                              n - 1, w, h, n, dt)}
     h, w = img.shape
     # calibrate on a thin band, then time a band sized for ~seconds_target
     probe = np.ascontiguousarray(img[: min(h, 16 + 2 * r)])
@@ -192,7 +213,9 @@ def main():
     import paper_1105_3829_amd as hrrm
 
     img, desc = workload(args.workload, args.r)
-    h, w = img.shape
+    vol = img.ndim == 3
+    depth = img.shape[0] if vol else 1
+    h, w = img.shape[-2:]
     dev = torch.device("cuda:0")
     host = torch.from_numpy(img)
     if host.dtype == torch.uint16:
@@ -207,8 +230,12 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     def step(i):
-        ctx.median2d(srcs[i % copies], args.r, variant=args.variant, out=outs[i % copies],
-                     stream=stream)
+        if vol:
+            ctx.median3d(srcs[i % copies], args.r, variant=args.variant, out=outs[i % copies],
+                         stream=stream)
+        else:
+            ctx.median2d(srcs[i % copies], args.r, variant=args.variant, out=outs[i % copies],
+                         stream=stream)
 
     for i in range(args.warmup):
         step(i)
@@ -230,10 +257,10 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    pixels = h * w
+    pixels = h * w * depth
     value = pixels / (ms_per_step * 1e-3) / 1e6
 
-    a_ops, zbar, d = lds_work_per_pixel(img, args.variant)
+    a_ops, zbar, d = lds_work_per_pixel(img, args.variant, args.r)
     lds_bytes_launch = a_ops * 4.0 * pixels
     hbm_bytes_launch = 2.0 * img.dtype.itemsize * pixels
     lds_gbs = lds_bytes_launch / (kernel_ms * 1e-3) / 1e9
@@ -250,7 +277,7 @@ def main():
     res = {
         "metric": METRIC,
         "value": round(value, 2),
-        "unit": "Mpix/s",
+        "unit": "Mvox/s" if vol else "Mpix/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -260,9 +287,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u%d" % (8 * img.dtype.itemsize),
         "data": "synthetic",
-        "config": {"workload": "%s, r=%d (%dx%d window), clamp-to-edge, %s tree" % (
-            desc, args.r, 2 * args.r + 1, 2 * args.r + 1, args.variant), "width": w, "height": h,
-            "r": args.r, "variant": args.variant, "input_copies": copies},
+        "config": {"workload": "%s, r=%d (%s window), clamp-to-edge, %s tree" % (
+            desc, args.r, "x".join([str(2 * args.r + 1)] * (3 if vol else 2)), args.variant),
+            "width": w, "height": h, **({"depth": depth} if vol else {}), "r": args.r,
+            "variant": args.variant, "input_copies": copies},
         "roofline": {"bound": "lds", "achieved": round(lds_gbs, 2), "peak": LDS_PEAK_GBS,
                      "unit": "GB/s", "frac": round(lds_gbs / LDS_PEAK_GBS, 5),
                      "traffic": traffic, "kernel_ms": round(kernel_ms, 4),
