@@ -14,7 +14,9 @@ Prints ONE JSON line.  Besides the throughput it carries
   * cpu_baseline: the brute-force CPU oracle timed on a band of full rows of
     the same image on this host's cores.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload c1] [--r 15]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload c0/c1/c2/c3] [--r 15]
+
+(c0, c1, c2: 2-D images; c3: the 16-bit 512 x 512 x 256 volume, 3-D windows.)
 """
 from __future__ import annotations
 
