@@ -928,7 +928,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
       // the wave builds each such subtree once in scratch.
       const uint64_t nos = ballot(act && slot < 0);
       bool use_raw = raw_fallback;
-      if (nos && !use_raw && !ADAPT) {
+      if (nos && !use_raw) {
         int g = 0;
         for (uint64_t t = nos; t && g <= gs; ++g) {
           const int leader = __builtin_ctzll(t);
