@@ -85,3 +85,28 @@ def test_autotune_cache_roundtrip(hrrm, tmp_path):
     ctx2.load_tuning(path)
     assert ctx2.get_tile(hrrm.U16, 2, 15).as_dict() == tuned
     assert "\"r\": 3" in open(path).read()
+
+
+@pytest.mark.parametrize("kind,r", [("u16", 9), ("u16", 20), ("u8", 12)])
+def test_wave_private_slots_rank_and_precision(hrrm, kind, r):
+    # other ranks and early stops with per-wave slots (deeper subtrees end at
+    # the stop depth; the descent is the median's with another K)
+    ctx = hrrm.Context(0)
+    if kind == "u8":
+        img, dt = datagen.uniform_u8(90, 520, seed=90 + r), hrrm.U8
+    else:
+        img, dt = datagen.xray_u16(90, 520, seed=90 + r), hrrm.U16
+    n = (2 * r + 1) ** 2
+    c = ctx.get_tile(dt, 2, r)
+    c.wave_slots, c.lds_budget = 1, 40 * 1024
+    ctx.set_tile(dt, 2, r, "plain", c)
+    d = to_dev(img)
+    for k in (0, n // 3, n - 1):
+        announce("wave slots rank", kind, r, k)
+        got = to_host(ctx.rank2d(d, r, k))
+        assert np.array_equal(got, oracle.rank2d(img, r, k)), k
+    for drop in (3, 6):
+        announce("wave slots drop", kind, r, drop)
+        got = to_host(ctx.rank2d(d, r, (n - 1) // 2, drop_levels=drop))
+        assert np.array_equal(got, oracle.rank2d(img, r, None, drop_bits=drop)), drop
+    ctx.set_tile(dt, 2, r, "plain", None)
