@@ -9,7 +9,7 @@ larger than the 256 MB last-level cache so every step reads from HBM.
 
 Prints ONE JSON line.  Besides the throughput it carries
   * roofline: the LDS bound of the kernel (algorithmic LDS work per pixel from
-    the input histogram, see DESIGN.md) against the LDS peak, the kernel time
+    the input histogram) against the LDS peak, the kernel time
     taken from HIP events on the launch stream, with the HBM view alongside;
   * cpu_baseline: the brute-force CPU oracle timed on a band of full rows of
     the same image on this host's cores.
@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "output Mpix/s (u16 4096², r=15) + % HBM/LDS roofline; serving p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
-# LDS: 256 CUs x 32 banks x 4 B per clock x 2.4 GHz (derivation in the design doc)
+# LDS: 256 CUs x 32 banks x 4 B per clock x 2.4 GHz
 LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
 
 
@@ -205,8 +205,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the filter would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the filter "
+              "would shard into row bands with r halo rows, one per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -44,7 +44,7 @@ extern "C" {
 #define HRRM_OK 0
 #define HRRM_EINVAL (-1)       /* bad argument (null pointer, bad size, overlap ...) */
 #define HRRM_ENOMEM (-2)       /* device memory for a workspace could not be obtained */
-#define HRRM_EUNSUPPORTED (-3) /* valid request outside what this build supports */
+#define HRRM_EUNSUPPORTED (-3) /* valid request outside what the library supports */
 #define HRRM_EDEVICE (-4)      /* a HIP runtime call failed */
 #define HRRM_EAGAIN (-5)       /* try again later (serving queue full / not finished) */
 
