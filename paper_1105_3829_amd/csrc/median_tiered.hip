@@ -44,6 +44,8 @@
 #include "hrrm_internal.h"
 #include "wave.hpp"
 
+#include <type_traits>
+
 namespace hrrm {
 namespace {
 
@@ -412,6 +414,28 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
   const int r = a.r, zr = D3 ? r : 0, stop = a.stop;
   const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
   if constexpr (NB <= 1) {  // one row at a time: fewest registers
+    if constexpr (D3) {  // stepped row offsets (measured faster here)
+      for (int c = lane; c <= 64 + span - 1; c += 64) {
+        const T* col = src + clampi(x0w - r - 1 + c, a.w - 1);
+        uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+        RowWalk<D3> rw(y, z, a.h, a.d, a.srs, a.sss, r, zr);
+        for (int dz = -zr; dz <= zr; ++dz) {
+#pragma unroll 4
+          for (int j = -r; j <= r; ++j) {
+            const int v = col[rw.off];
+            rw.next();
+            if (v >= rlo && v <= rhi) {
+              if constexpr (ADAPT)
+                acc = add4(acc, amask(topo, node, rdep, stop, v));
+              else
+                acc = add4(acc, and4(ts->lut[nib(v, rdep, bits)], lim));
+            }
+          }
+        }
+        *(uint4*)(scr + (size_t)c * 16) = acc;
+      }
+      return;
+    }
     for (int c = lane; c <= 64 + span - 1; c += 64) {
       const int64_t cx = clampi(x0w - r - 1 + c, a.w - 1);
       uint4 acc = make_uint4(0u, 0u, 0u, 0u);
@@ -435,6 +459,33 @@ __device__ __forceinline__ void scratch_build(uint8_t* scr, const T* __restrict_
   // the (2zr + 1) x span window rows of each column, slice-major, NB loaded
   // before any is used (their latencies overlap)
   const int nrows = (2 * zr + 1) * span;
+  if constexpr (sizeof(T) == 2) {  // stepped row offsets (measured faster here)
+    for (int c = lane; c <= 64 + span - 1; c += 64) {
+      const T* col = src + clampi(x0w - r - 1 + c, a.w - 1);
+      uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+      RowWalk<D3> rw(y, z, a.h, a.d, a.srs, a.sss, r, zr);
+      for (int q0 = 0; q0 < nrows; q0 += NB) {
+        int v[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          // rows past the window are clamped into the image, loaded and skipped
+          v[k] = col[rw.off];
+          rw.next();
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          if (q0 + k < nrows && v[k] >= rlo && v[k] <= rhi) {
+            if constexpr (ADAPT)
+              acc = add4(acc, amask(topo, node, rdep, stop, v[k]));
+            else
+              acc = add4(acc, and4(ts->lut[nib(v[k], rdep, bits)], lim));
+          }
+        }
+      }
+      *(uint4*)(scr + (size_t)c * 16) = acc;
+    }
+    return;
+  }
   for (int c = lane; c <= 64 + span - 1; c += 64) {
     const int64_t cx = clampi(x0w - r - 1 + c, a.w - 1);
     uint4 acc = make_uint4(0u, 0u, 0u, 0u);
@@ -1149,52 +1200,112 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
           // owns columns tid and tid + 256: no atomics, no barrier between
           // clear and fill).  The rows of both columns are loaded kRebRows at
           // a time before any is used, so their latencies overlap.
-          const bool two = tid + kBlock < ncols;
-          const int64_t cx0 = clampi(x0 - r - 1 + tid, a.w - 1);
-          const int64_t cx1 = clampi(x0 - r - 1 + tid + kBlock, a.w - 1);
-          for (int i = 0; i < nreb; ++i) {
-            const int rs = ts->reb[i][0], rlo = ts->reb[i][2];
-            const int rdep = ts->reb[i][3];
-            const int rhi = ts->hi[rs];
-            const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
-            auto tmask = [&](int v) -> uint4 {
-              if constexpr (ADAPT) {
-                int nx;
-                return smask(stopo + rs * 16, rdep, stop, v, &nx);
-              } else {
-                return and4(ts->lut[nib(v, rdep, bits)], lim);
-              }
-            };
-            uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
-            // the (2zr + 1) x span window rows of the columns, slice-major;
-            // (dz, j) walks them kRebRows at a time
-            const int nrows = (2 * zr + 1) * span;
-            int dz = -zr, j = -r;
-            for (int q0 = 0; q0 < nrows; q0 += kRebRows) {
-              int v0[kRebRows], v1[kRebRows];
-#pragma unroll
-              for (int k = 0; k < kRebRows; ++k) {
-                // rows past the window (slice zr + 1 onwards) are clamped into
-                // the volume, loaded and skipped
-                const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
-                const int64_t off = zz * a.sss + clampi(y + j, a.h - 1) * a.srs;
-                v0[k] = src[off + cx0];
-                v1[k] = two ? (int)src[off + cx1] : -1;
-                if (++j > r) {
-                  j = -r;
-                  ++dz;
+          // Two forms, each where it measured faster: 16-bit builds with
+          // matrix cores step the row offsets (RowWalk) and load second
+          // columns wave by wave; the others clamp each row's offset and load
+          // second columns under the lanes' own mask.
+          if constexpr (sizeof(T) == 2 && MF) {
+            const bool two = tid + kBlock < ncols;
+            const T* col0 = src + clampi(x0 - r - 1 + tid, a.w - 1);
+            const T* col1 = src + clampi(x0 - r - 1 + tid + kBlock, a.w - 1);
+            // a wave that holds any second column loads it on every lane (the
+            // column is clamped into the image, so the address is valid)
+            const bool wave_two = __builtin_amdgcn_readfirstlane((tid & ~63) + kBlock < ncols);
+            for (int i = 0; i < nreb; ++i) {
+              const int rs = ts->reb[i][0], rlo = ts->reb[i][2];
+              const int rdep = ts->reb[i][3];
+              const int rhi = ts->hi[rs];
+              const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+              auto tmask = [&](int v) -> uint4 {
+                if constexpr (ADAPT) {
+                  int nx;
+                  return smask(stopo + rs * 16, rdep, stop, v, &nx);
+                } else {
+                  return and4(ts->lut[nib(v, rdep, bits)], lim);
                 }
-              }
+              };
+              // the (2zr + 1) x span window rows of the columns, slice-major,
+              // kRebRows at a time; ALL: second columns loaded on every lane
+              auto fill = [&](auto all_tag) {
+                constexpr bool ALL = decltype(all_tag)::value;
+                uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
+                const int nrows = (2 * zr + 1) * span;
+                RowWalk<D3> rw(y, z, a.h, a.d, a.srs, a.sss, r, zr);
+                for (int q0 = 0; q0 < nrows; q0 += kRebRows) {
+                  int v0[kRebRows], v1[kRebRows];
 #pragma unroll
-              for (int k = 0; k < kRebRows; ++k) {
-                if (q0 + k < nrows) {
-                  if (v0[k] >= rlo && v0[k] <= rhi) c0 = add4(c0, tmask(v0[k]));
-                  if (v1[k] >= rlo && v1[k] <= rhi) c1 = add4(c1, tmask(v1[k]));
+                  for (int k = 0; k < kRebRows; ++k) {
+                    // rows past the window (slice zr + 1 onwards) are clamped
+                    // into the volume, loaded and skipped
+                    v0[k] = col0[rw.off];
+                    v1[k] = ALL ? (int)col1[rw.off] : -1;
+                    rw.next();
+                  }
+#pragma unroll
+                  for (int k = 0; k < kRebRows; ++k) {
+                    if (ALL && !two) v1[k] = -1;
+                    if (q0 + k < nrows) {
+                      if (v0[k] >= rlo && v0[k] <= rhi) c0 = add4(c0, tmask(v0[k]));
+                      if (ALL && v1[k] >= rlo && v1[k] <= rhi) c1 = add4(c1, tmask(v1[k]));
+                    }
+                  }
                 }
-              }
+                vec(slots, cp16, rs, tid) = c0;
+                if (two) vec(slots, cp16, rs, tid + kBlock) = c1;
+              };
+              if (wave_two)
+                fill(std::true_type{});
+              else
+                fill(std::false_type{});
             }
-            vec(slots, cp16, rs, tid) = c0;
-            if (two) vec(slots, cp16, rs, tid + kBlock) = c1;
+          } else {
+            const bool two = tid + kBlock < ncols;
+            const int64_t cx0 = clampi(x0 - r - 1 + tid, a.w - 1);
+            const int64_t cx1 = clampi(x0 - r - 1 + tid + kBlock, a.w - 1);
+            for (int i = 0; i < nreb; ++i) {
+              const int rs = ts->reb[i][0], rlo = ts->reb[i][2];
+              const int rdep = ts->reb[i][3];
+              const int rhi = ts->hi[rs];
+              const uint4 lim = level_mask(stop - rdep < kTierLevels ? stop - rdep : kTierLevels);
+              auto tmask = [&](int v) -> uint4 {
+                if constexpr (ADAPT) {
+                  int nx;
+                  return smask(stopo + rs * 16, rdep, stop, v, &nx);
+                } else {
+                  return and4(ts->lut[nib(v, rdep, bits)], lim);
+                }
+              };
+              uint4 c0 = make_uint4(0u, 0u, 0u, 0u), c1 = c0;
+              // the (2zr + 1) x span window rows of the columns, slice-major;
+              // (dz, j) walks them kRebRows at a time
+              const int nrows = (2 * zr + 1) * span;
+              int dz = -zr, j = -r;
+              for (int q0 = 0; q0 < nrows; q0 += kRebRows) {
+                int v0[kRebRows], v1[kRebRows];
+#pragma unroll
+                for (int k = 0; k < kRebRows; ++k) {
+                  // rows past the window (slice zr + 1 onwards) are clamped into
+                  // the volume, loaded and skipped
+                  const int64_t zz = D3 ? clampi(z + dz, a.d - 1) : z;
+                  const int64_t off = zz * a.sss + clampi(y + j, a.h - 1) * a.srs;
+                  v0[k] = src[off + cx0];
+                  v1[k] = two ? (int)src[off + cx1] : -1;
+                  if (++j > r) {
+                    j = -r;
+                    ++dz;
+                  }
+                }
+#pragma unroll
+                for (int k = 0; k < kRebRows; ++k) {
+                  if (q0 + k < nrows) {
+                    if (v0[k] >= rlo && v0[k] <= rhi) c0 = add4(c0, tmask(v0[k]));
+                    if (v1[k] >= rlo && v1[k] <= rhi) c1 = add4(c1, tmask(v1[k]));
+                  }
+                }
+              }
+              vec(slots, cp16, rs, tid) = c0;
+              if (two) vec(slots, cp16, rs, tid + kBlock) = c1;
+            }
           }
           __syncthreads();
         }

@@ -30,6 +30,51 @@ __device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) {
   return v < 0 ? 0 : (v > hi ? hi : v);
 }
 
+// Element offsets of the clamped window rows (z + dz, y + j) of one output
+// pixel, one row per next(): j = -r..r within each slice dz = -zr..zr,
+// slice-major (3-D), or j = -r, -r + 1, ... (2-D).  The offset moves on by a
+// row (slice) stride only where the step stays inside the image, so
+// clamp-to-edge repeats the edge row with no per-row 64-bit clamp or
+// multiply.  Past the last window row the walk goes on with rows still
+// clamped into the image (valid addresses).
+template <bool D3>
+struct RowWalk {
+  int64_t off, top, srs, sss;  // current offset; offset of row j = -r in the current slice
+  int j, dz, r;
+  // the step j -> j + 1 moves down a row iff 0 <= j - jlo < jn (rows y + j
+  // and y + j + 1 both inside 0..h-1); the same for slices with zlo, zn
+  int jlo, jn, zlo, zn;
+  __device__ __forceinline__ RowWalk(int64_t y, int64_t z, int64_t h, int64_t d, int64_t srs_,
+                                     int64_t sss_, int r_, int zr)
+      : srs(srs_), sss(sss_), j(-r_), dz(-zr), r(r_) {
+    // bounds of the advancing steps, limited to the walk's own range
+    auto lim = [&](int64_t v) -> int {
+      const int64_t m = 4 * (int64_t)r_ + 16;
+      return (int)(v < -m ? -m : v > m ? m : v);
+    };
+    jlo = lim(-y);
+    jn = lim(h - 2 - y) - jlo + 1;
+    jn = jn < 0 ? 0 : jn;
+    zlo = lim(-z);
+    zn = lim(d - 2 - z) - zlo + 1;
+    zn = zn < 0 ? 0 : zn;
+    const int64_t zz = D3 ? clampi(z - zr, d - 1) : z;
+    top = zz * sss + clampi(y - r_, h - 1) * srs;
+    off = top;
+  }
+  __device__ __forceinline__ void next() {
+    if (!D3 || j < r) {
+      off += (uint32_t)(j - jlo) < (uint32_t)jn ? srs : 0;
+      ++j;
+    } else {
+      j = -r;
+      top += (uint32_t)(dz - zlo) < (uint32_t)zn ? sss : 0;
+      ++dz;
+      off = top;
+    }
+  }
+};
+
 __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 // Workgroup tile from blockIdx: consecutive workgroups land on consecutive
