@@ -47,7 +47,9 @@ struct RowWalk {
   __device__ __forceinline__ RowWalk(int64_t y, int64_t z, int64_t h, int64_t d, int64_t srs_,
                                      int64_t sss_, int r_, int zr)
       : srs(srs_), sss(sss_), j(-r_), dz(-zr), r(r_) {
-    // bounds of the advancing steps, limited to the walk's own range
+    // bounds of the advancing steps, cut to +-(4r + 16) so they fit an int:
+    // exact while j and dz stay within that range (a walk covers its window
+    // plus at most one batch of rows past it)
     auto lim = [&](int64_t v) -> int {
       const int64_t m = 4 * (int64_t)r_ + 16;
       return (int)(v < -m ? -m : v > m ? m : v);
