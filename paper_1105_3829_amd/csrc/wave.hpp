@@ -26,7 +26,7 @@ __device__ __forceinline__ uint32_t wave_scan(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) {
+__host__ __device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) {
   return v < 0 ? 0 : (v > hi ? hi : v);
 }
 
@@ -44,8 +44,8 @@ struct RowWalk {
   // the step j -> j + 1 moves down a row iff 0 <= j - jlo < jn (rows y + j
   // and y + j + 1 both inside 0..h-1); the same for slices with zlo, zn
   int jlo, jn, zlo, zn;
-  __device__ __forceinline__ RowWalk(int64_t y, int64_t z, int64_t h, int64_t d, int64_t srs_,
-                                     int64_t sss_, int r_, int zr)
+  __host__ __device__ __forceinline__ RowWalk(int64_t y, int64_t z, int64_t h, int64_t d,
+                                              int64_t srs_, int64_t sss_, int r_, int zr)
       : srs(srs_), sss(sss_), j(-r_), dz(-zr), r(r_) {
     // bounds of the advancing steps, cut to +-(4r + 16) so they fit an int:
     // exact while j and dz stay within that range (a walk covers its window
@@ -64,7 +64,7 @@ struct RowWalk {
     top = zz * sss + clampi(y - r_, h - 1) * srs;
     off = top;
   }
-  __device__ __forceinline__ void next() {
+  __host__ __device__ __forceinline__ void next() {
     if (!D3 || j < r) {
       off += (uint32_t)(j - jlo) < (uint32_t)jn ? srs : 0;
       ++j;
