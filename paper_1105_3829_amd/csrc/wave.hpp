@@ -82,7 +82,7 @@ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t
 // Workgroup tile from blockIdx: consecutive workgroups land on consecutive
 // XCDs; remap so that each XCD works on a contiguous band of tiles (shared
 // halos stay in that XCD's L2).
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+__host__ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   const int q = nb >> 3, rem = nb & 7, xcd = bid & 7, i = bid >> 3;
   return xcd * q + (xcd < rem ? xcd : rem) + i;
 }
