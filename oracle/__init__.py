@@ -42,13 +42,15 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
             lib.oracle_rank2d.argtypes = [i32, vp, vp, i64, i64, i64, i64, i32, i64, i32, i32]
+            lib.oracle_rank2d_u8_thresholds.argtypes = [vp, vp, i64, i64, i64, i64, i32, i64,
+                                                        i32]
             lib.oracle_rank3d.argtypes = [i32, vp, vp, i64, i64, i64, i64, i64, i64, i64, i32,
                                           i64, i32]
             lib.oracle_rank2d_at.argtypes = [i32, vp, i64, i64, i64, i32, i64, vp, vp, i64, vp,
                                              i32]
             lib.oracle_rank3d_at.argtypes = [i32, vp, i64, i64, i64, i64, i64, i32, i64, vp, vp,
                                              vp, i64, vp, i32]
-            for f in (lib.oracle_rank2d, lib.oracle_rank3d, lib.oracle_rank2d_at,
+            for f in (lib.oracle_rank2d, lib.oracle_rank2d_u8_thresholds, lib.oracle_rank3d, lib.oracle_rank2d_at,
                       lib.oracle_rank3d_at, lib.oracle_default_threads):
                 f.restype = ctypes.c_int
             _lib = lib
@@ -95,6 +97,26 @@ def rank2d(img: np.ndarray, r: int, k: int | None = None, drop_bits: int = 0,
 
 def median2d(img: np.ndarray, r: int, threads: int = 0) -> np.ndarray:
     return rank2d(img, r, None, 0, threads)
+
+
+def rank2d_u8_thresholds(img: np.ndarray, r: int, k: int | None = None,
+                         threads: int = 0) -> np.ndarray:
+    """Same filter as rank2d for uint8 images, computed by threshold
+    decomposition (stacking property): out >= t iff at least N - k window
+    values are >= t.  Its cost does not depend on r."""
+    img = np.ascontiguousarray(img)
+    assert img.ndim == 2 and img.dtype == np.uint8
+    h, w = img.shape
+    if k is None:
+        k = median_rank(r, 2)
+    out = np.empty_like(img)
+    if h == 0 or w == 0:
+        return out
+    rc = _load().oracle_rank2d_u8_thresholds(img.ctypes.data, out.ctypes.data, w, h, w, w, r, k,
+                                             threads)
+    if rc != 0:
+        raise ValueError("oracle_rank2d_u8_thresholds rejected its arguments")
+    return out
 
 
 def rank3d(vol: np.ndarray, r: int, k: int | None = None, threads: int = 0) -> np.ndarray:

@@ -24,6 +24,15 @@
 // values containing it, so the result is the exact order statistic with its
 // b low bits cleared; the drop_bits argument of oracle_rank2d does exactly that.
 //
+// Threshold decomposition (8-bit images only, oracle_rank2d_u8_thresholds):
+// a second, independent route to the same rank-K filter, from the stacking
+// property of rank filters: the K-th smallest value m of a window satisfies
+// m >= t exactly when at least N - K window values are >= t.  So
+//   out = sum over t = 1..255 of [ #{window values >= t} >= N - K ],
+// and each count is a plain box sum of the binary image [in >= t], taken from
+// a summed-area table of the clamp-extended image.  The cost does not grow
+// with r, which makes full-size 8192 x 8192 references at r = 100 affordable.
+//
 // Parity pinning lives in tests/test_oracle.py (brute-force counting on tiny
 // inputs, certificates, invariances, threshold decomposition).
 #include <algorithm>
@@ -151,6 +160,55 @@ void rank3d_at(const T* src, int64_t w, int64_t h, int64_t d, int64_t rs, int64_
   });
 }
 
+// Rank-k filter of an 8-bit image by threshold decomposition (see the file
+// comment).  Rows are handled in bands of `band` rows; each band builds, per
+// threshold, the summed-area table of its clamp-extended rows and columns.
+void rank2d_u8_thresholds(const uint8_t* src, uint8_t* dst, int64_t w, int64_t h, int64_t ss,
+                          int64_t ds, int r, int64_t k, int nthreads) {
+  const int64_t side = 2 * (int64_t)r + 1;
+  const int64_t need = side * side - k;  // #{>= t} needed for out >= t
+  const int64_t band = 256;
+  const int64_t nb = (h + band - 1) / band;
+  parallel_rows(nb, nthreads, [&](int64_t b) {
+    const int64_t y0 = b * band, y1 = std::min(h, y0 + band);
+    const int64_t eh = (y1 - y0) + 2 * r, ew = w + 2 * r;  // clamp-extended band
+    std::vector<uint8_t> ext((size_t)(eh * ew));
+    for (int64_t i = 0; i < eh; ++i) {
+      const int64_t yy = clampi(y0 - r + i, 0, h - 1);
+      for (int64_t j = 0; j < ew; ++j) ext[i * ew + j] = src[yy * ss + clampi(j - r, 0, w - 1)];
+    }
+    // sat[(i)(ew+1) + j] = number of ext values >= t in rows < i, columns < j
+    std::vector<int32_t> sat((size_t)((eh + 1) * (ew + 1)));
+    std::vector<int32_t> acc((size_t)((y1 - y0) * w), 0);
+    for (int t = 1; t <= 255; ++t) {
+      for (int64_t j = 0; j <= ew; ++j) sat[j] = 0;
+      for (int64_t i = 0; i < eh; ++i) {
+        int32_t row = 0;
+        sat[(i + 1) * (ew + 1)] = 0;
+        for (int64_t j = 0; j < ew; ++j) {
+          row += ext[i * ew + j] >= t ? 1 : 0;
+          sat[(i + 1) * (ew + 1) + j + 1] = sat[i * (ew + 1) + j + 1] + row;
+        }
+      }
+      bool any = false;
+      for (int64_t y = 0; y < y1 - y0; ++y)
+        for (int64_t x = 0; x < w; ++x) {
+          // window rows y .. y + 2r, columns x .. x + 2r of the extended band
+          const int64_t cnt = (int64_t)sat[(y + side) * (ew + 1) + x + side] -
+                              sat[y * (ew + 1) + x + side] - sat[(y + side) * (ew + 1) + x] +
+                              sat[y * (ew + 1) + x];
+          if (cnt >= need) {
+            ++acc[y * w + x];
+            any = true;
+          }
+        }
+      if (!any) break;  // counts only fall as t grows
+    }
+    for (int64_t y = 0; y < y1 - y0; ++y)
+      for (int64_t x = 0; x < w; ++x) dst[(y0 + y) * ds + x] = (uint8_t)acc[y * w + x];
+  });
+}
+
 bool bad2d(int bytes, const void* src, int64_t w, int64_t h, int64_t ss, int r, int64_t k,
            int dims) {
   if (bytes != 1 && bytes != 2) return true;
@@ -185,6 +243,18 @@ int oracle_rank2d(int bytes, const void* src, void* dst, int64_t w, int64_t h,
   else
     rank2d((const uint16_t*)src, (uint16_t*)dst, w, h, src_stride, dst_stride, r, k, drop_bits,
            nthreads);
+  return 0;
+}
+
+// Rank-k filter of an 8-bit image over (2r+1)^2 clamp-to-edge windows by
+// threshold decomposition (independent of oracle_rank2d's selection).
+// Returns 0, or -1 on a bad argument.
+int oracle_rank2d_u8_thresholds(const void* src, void* dst, int64_t w, int64_t h,
+                                int64_t src_stride, int64_t dst_stride, int r, int64_t k,
+                                int nthreads) {
+  if (bad2d(1, src, w, h, src_stride, r, k, 2) || !dst || dst_stride < w) return -1;
+  rank2d_u8_thresholds((const uint8_t*)src, (uint8_t*)dst, w, h, src_stride, dst_stride, r, k,
+                       nthreads);
   return 0;
 }
 

@@ -15,6 +15,7 @@
 #include "hrrm.h"
 #include "hrrm_ctx.h"
 #include "hrrm_internal.h"
+#include "host_logic.hpp"
 
 namespace hrrm {
 
@@ -180,37 +181,14 @@ TileConfig Context::tile_for(int bytes, int dims, int r, bool adaptive, int64_t 
 
 // ---- validation --------------------------------------------------------------
 
-static bool overlap(const void* a, size_t an, const void* b, size_t bn) {
-  const char* pa = (const char*)a;
-  const char* pb = (const char*)b;
-  return pa < pb + bn && pb < pa + an;
-}
-
 int validate(const void* src, const void* dst, int dtype, int64_t w, int64_t h, int64_t d,
              int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r, int dims) {
-  if (dtype != HRRM_U8 && dtype != HRRM_U16) return fail(HRRM_EINVAL, "unknown dtype %d", dtype);
-  if (w < 0 || h < 0 || d < 0) return fail(HRRM_EINVAL, "negative image size");
-  if (r < 0) return fail(HRRM_EINVAL, "negative radius %d", r);
-  const int maxr = dims == 2 ? HRRM_MAX_R_2D : HRRM_MAX_R_3D;
-  if (r > maxr)
-    return fail(HRRM_EUNSUPPORTED, "radius %d above the supported maximum %d for %d-D", r, maxr,
-                dims);
-  if (w == 0 || h == 0 || d == 0) return HRRM_OK;
-  if (!src || !dst) return fail(HRRM_EINVAL, "null image pointer");
-  if (srs < w || drs < w) return fail(HRRM_EINVAL, "row stride smaller than width");
-  if (dims == 3 && (sss < srs * h || dss < drs * h))
-    return fail(HRRM_EINVAL, "slice stride smaller than row_stride * height");
-  const int bytes = dtype == HRRM_U8 ? 1 : 2;
-  if (bytes == 2 && ((((uintptr_t)src) | ((uintptr_t)dst)) & 1))
-    return fail(HRRM_EINVAL, "uint16 buffer not 2-byte aligned");
-  const int64_t limit = (int64_t)1 << 40;
-  if (w > limit || h > limit || d > limit || srs > limit || drs > limit)
-    return fail(HRRM_EINVAL, "image dimensions out of range");
-  const size_t sbytes =
-      (size_t)bytes * (size_t)(dims == 3 ? (d - 1) * sss + (h - 1) * srs + w : (h - 1) * srs + w);
-  const size_t dbytes =
-      (size_t)bytes * (size_t)(dims == 3 ? (d - 1) * dss + (h - 1) * drs + w : (h - 1) * drs + w);
-  if (overlap(src, sbytes, dst, dbytes)) return fail(HRRM_EINVAL, "src and dst overlap");
+  const char* why = "";
+  const int rc = check_image_args(src, dst, dtype, w, h, d, srs, sss, drs, dss, r, dims, &why);
+  if (rc == HRRM_EUNSUPPORTED)
+    return fail(rc, "%s (radius %d, at most %d for %d-D)", why, r,
+                dims == 2 ? HRRM_MAX_R_2D : HRRM_MAX_R_3D, dims);
+  if (rc != HRRM_OK) return fail(rc, "%s", why);
   return HRRM_OK;
 }
 

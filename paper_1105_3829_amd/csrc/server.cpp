@@ -31,62 +31,16 @@
 
 #include "hrrm.h"
 #include "hrrm_ctx.h"
+#include "host_logic.hpp"
 
 namespace hrrm {
 
 namespace {
 
-constexpr size_t kAlign = 256;
 constexpr int kBypass = 8;
 constexpr int kStreams = 2;
 
-size_t round_up(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
-
-// First-fit sub-allocator over offsets of one device arena; frees coalesce.
-class Arena {
- public:
-  void reset(size_t n) {
-    free_.clear();
-    if (n) free_[0] = n;
-    used_ = 0;
-  }
-  bool alloc(size_t n, size_t* off) {
-    n = round_up(n);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        const size_t base = it->first, rest = it->second - n;
-        free_.erase(it);
-        if (rest) free_[base + n] = rest;
-        *off = base;
-        used_ += n;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    n = round_up(n);
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t used() const { return used_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t used_ = 0;
-};
+size_t round_up(size_t n) { return Arena::round_up(n); }
 
 enum class St { Queued, Admitted, Done };
 
@@ -157,48 +111,52 @@ bool Server::step() {
       ++i;
     }
   }
-  // 2. admission
-  int passed = 0;
-  for (auto qi = queue.begin(); qi != queue.end() && inflight < max_inflight;) {
-    Item& r = items[*qi];
-    size_t oi = 0, oo = 0;
-    if (!arena.alloc(r.in_bytes, &oi)) {
-      if (++passed > kBypass) break;
-      ++qi;
-      continue;
+  // 2. admission (the rule itself is host_logic.hpp's plan_admission)
+  if (!queue.empty() && inflight < max_inflight) {
+    std::vector<std::pair<size_t, size_t>> need;
+    need.reserve(queue.size());
+    for (uint64_t tk : queue) {
+      const Item& r = items[tk];
+      need.emplace_back(r.in_bytes, r.out_bytes);
     }
-    if (!arena.alloc(r.out_bytes, &oo)) {
-      arena.release(oi, r.in_bytes);
-      if (++passed > kBypass) break;
-      ++qi;
-      continue;
+    const std::vector<Admitted> plan =
+        plan_admission(arena, need, max_inflight - inflight, kBypass);
+    std::vector<bool> taken(queue.size(), false);
+    for (const Admitted& p : plan) {
+      const uint64_t tk = queue[p.index];
+      Item& r = items[tk];
+      taken[p.index] = true;
+      r.off_in = p.off_in;
+      r.off_out = p.off_out;
+      const size_t b = bpp(r.req.dtype);
+      // packed rows: one linear copy (full link speed from pinned memory);
+      // strided rows: a 2-D copy, which the runtime performs far more slowly
+      hipError_t e =
+          r.req.src_row_stride == r.req.width
+              ? hipMemcpyAsync(base + r.off_in, r.req.src, r.in_bytes, hipMemcpyHostToDevice, copy)
+              : hipMemcpy2DAsync(base + r.off_in, (size_t)r.req.width * b, r.req.src,
+                                 (size_t)r.req.src_row_stride * b, (size_t)r.req.width * b,
+                                 (size_t)r.req.height, hipMemcpyHostToDevice, copy);
+      r.st = St::Admitted;
+      r.t_admit = now();
+      ++inflight;
+      if (e != hipSuccess) {  // the request fails; its input buffer is returned at once
+        r.status = HRRM_EDEVICE;
+        r.st = St::Done;
+        r.t_done = r.t_admit;
+        arena.release(r.off_in, r.in_bytes);
+        finished.push_back(tk);
+      } else {
+        staged.push_back(tk);
+      }
+      did = true;
     }
-    r.off_in = oi;
-    r.off_out = oo;
-    const size_t b = bpp(r.req.dtype);
-    // packed rows: one linear copy (full link speed from pinned memory); strided
-    // rows: a 2-D copy, which the runtime performs far more slowly
-    hipError_t e = r.req.src_row_stride == r.req.width
-                       ? hipMemcpyAsync(base + oi, r.req.src, r.in_bytes, hipMemcpyHostToDevice,
-                                        copy)
-                       : hipMemcpy2DAsync(base + oi, (size_t)r.req.width * b, r.req.src,
-                                          (size_t)r.req.src_row_stride * b,
-                                          (size_t)r.req.width * b, (size_t)r.req.height,
-                                          hipMemcpyHostToDevice, copy);
-    r.st = St::Admitted;
-    r.t_admit = now();
-    ++inflight;
-    if (e != hipSuccess) {  // the request fails; its buffers are returned at once
-      r.status = HRRM_EDEVICE;
-      r.st = St::Done;
-      r.t_done = r.t_admit;
-      arena.release(oi, r.in_bytes);
-      finished.push_back(*qi);
-    } else {
-      staged.push_back(*qi);
+    if (!plan.empty()) {
+      std::deque<uint64_t> rest;
+      for (size_t i = 0; i < queue.size(); ++i)
+        if (!taken[i]) rest.push_back(queue[i]);
+      queue.swap(rest);
     }
-    qi = queue.erase(qi);
-    did = true;
   }
   // 3. launch what was admitted
   if (!staged.empty() && (int)running.size() < kStreams) {

@@ -22,6 +22,7 @@
 #include "hrrm.h"
 #include "hrrm_ctx.h"
 #include "hrrm_internal.h"
+#include "host_logic.hpp"
 
 namespace hrrm {
 
@@ -92,40 +93,18 @@ int save_tuning(const Context* c, const char* path) {
   return HRRM_OK;
 }
 
-static bool field(const char* line, const char* name, double* out) {
-  std::string key = std::string("\"") + name + "\":";
-  const char* p = strstr(line, key.c_str());
-  if (!p) return false;
-  *out = strtod(p + key.size(), nullptr);
-  return true;
-}
-
 int load_tuning(Context* c, const char* path) {
   FILE* f = fopen(path, "r");
   if (!f) return fail(HRRM_EINVAL, "cannot read %s", path);
   char line[1024];
   std::vector<TunedEntry> got;
   while (fgets(line, sizeof line, f)) {
-    double v[13];
-    const char* names[13] = {"bytes",      "dims",      "r",  "adaptive",   "seg_rows",
-                             "nslots",     "min_group", "max_groups",       "lds_budget",
-                             "tiered_u8",  "ms",        "raw_window",       "wave_slots"};
-    bool ok = true;
-    for (int i = 0; i < 11 && ok; ++i) ok = field(line, names[i], &v[i]);
-    if (!ok) continue;
-    if (!field(line, names[11], &v[11])) v[11] = 49;
-    if (!field(line, names[12], &v[12])) v[12] = 0;
-    TunedEntry e{(int)v[0], (int)v[1], (int)v[2], (int)v[3],
-                 TileConfig{(int32_t)v[4], (int32_t)v[5], (int32_t)v[6], (int32_t)v[7],
-                            (int32_t)v[8], (int32_t)v[9], (int32_t)v[11], (int32_t)v[12]},
-                 v[10]};
-    const TileConfig& t = e.cfg;
-    if ((e.bytes != 1 && e.bytes != 2) || (e.dims != 2 && e.dims != 3) || e.r < 0 ||
-        t.seg_rows < 1 || t.nslots < 0 || t.nslots > kMaxSlots || t.min_group < 1 ||
-        t.max_groups < 0 || t.lds_budget < 16 * 1024 || t.lds_budget > kLdsLimit ||
-        t.raw_window < 0 || (t.wave_slots != 0 && t.wave_slots != 1))
-      continue;
-    got.push_back(e);
+    TuningLine t;
+    if (!parse_tuning_line(line, &t, kMaxSlots, kLdsLimit)) continue;
+    got.push_back(TunedEntry{t.bytes, t.dims, t.r, t.adaptive,
+                             TileConfig{t.seg_rows, t.nslots, t.min_group, t.max_groups,
+                                        t.lds_budget, t.tiered_u8, t.raw_window, t.wave_slots},
+                             t.ms});
   }
   fclose(f);
   for (const TunedEntry& e : got) {

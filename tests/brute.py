@@ -59,6 +59,23 @@ def median_by_thresholds_u8(img: np.ndarray, r: int) -> np.ndarray:
     return out.astype(np.uint8)
 
 
+def rank_dropped_by_coarse_counts(img: np.ndarray, r: int, dims: int, k: int, b: int) -> np.ndarray:
+    """Variable precision (Sec. III-D), from counts alone: a descent of the
+    uniform tree stopped b levels above the leaves ends in the aligned block of
+    2^b grey values that holds the k-th smallest value m and returns its lower
+    bound, 2^b * floor(m / 2^b).  That bound is 2^b times the number of t >= 1
+    with t * 2^b <= m, and t * 2^b <= m holds exactly when at least N - k
+    window values are >= t * 2^b (the stacking property).  No selection, no
+    bit mask."""
+    w = windows(img, r, dims).astype(np.int64)
+    n = w.shape[-1]
+    top = 1 << (8 * img.dtype.itemsize)
+    out = np.zeros(img.shape, dtype=np.int64)
+    for t in range(1, (top >> b) + 1):
+        out += (w >= t << b).sum(-1) >= n - k
+    return (out << b).astype(img.dtype)
+
+
 def certificate_ok(img: np.ndarray, out: np.ndarray, r: int, dims: int, k: int) -> bool:
     """m is in the window and #{u < m} <= k < #{u <= m}."""
     w = windows(img, r, dims).astype(np.int64)

@@ -188,6 +188,26 @@ def test_threshold_decomposition_u8(oracle_mod, r):
     np.testing.assert_array_equal(oracle_mod.median2d(low, r), brute.median_by_thresholds_u8(low, r))
 
 
+@pytest.mark.parametrize("r", [0, 1, 2, 5, 17, 40])
+def test_threshold_path_equals_selection(oracle_mod, r):
+    # the oracle's two routes to the 8-bit rank filter (nth_element per window,
+    # threshold decomposition with box counts) must agree everywhere
+    g = np.random.default_rng(300 + r)
+    shapes = [(1, 1), (1, 7), (5, 1), (33, 47), (70, 130)]
+    for h, w in shapes:
+        img = g.integers(0, 256, size=(h, w)).astype(np.uint8)
+        n = (2 * r + 1) ** 2
+        for k in sorted({0, (n - 1) // 2, n - 1, n // 3}):
+            np.testing.assert_array_equal(oracle_mod.rank2d_u8_thresholds(img, r, k),
+                                          oracle_mod.rank2d(img, r, k))
+    ext = np.where(g.random((40, 50)) < 0.5, 0, 255).astype(np.uint8)  # only the extremes
+    np.testing.assert_array_equal(oracle_mod.rank2d_u8_thresholds(ext, r),
+                                  oracle_mod.median2d(ext, r))
+    low = datagen.lowkey_u8(90, 61, seed=r)
+    np.testing.assert_array_equal(oracle_mod.rank2d_u8_thresholds(low, r),
+                                  brute.median_by_thresholds_u8(low, r))
+
+
 def test_rank_extremes_and_general(oracle_mod):
     g = np.random.default_rng(19)
     img = g.integers(0, 65536, size=(17, 23)).astype(np.uint16)
@@ -199,6 +219,23 @@ def test_rank_extremes_and_general(oracle_mod):
         for k in (1, n // 4, n - 2):
             np.testing.assert_array_equal(oracle_mod.rank2d(img, r, k),
                                           brute.rank_by_counting(img, r, 2, k))
+
+
+def test_reduced_precision_from_counts(oracle_mod):
+    # independent pin of the drop_bits branch: the early-stopped descent's
+    # lower bound computed from coarse threshold counts (tests/brute.py), with
+    # no selection and no bit mask
+    g = np.random.default_rng(41)
+    img16 = (g.integers(0, 64, size=(9, 11)) * 1031 % 65536).astype(np.uint16)
+    img8 = g.integers(0, 256, size=(10, 9)).astype(np.uint8)
+    for img, bits in ((img16, (0, 3, 9, 12, 16)), (img8, (0, 1, 4, 7, 8))):
+        for r in (1, 2):
+            n = (2 * r + 1) ** 2
+            for k in (0, (n - 1) // 2, n - 1):
+                for b in bits:
+                    np.testing.assert_array_equal(
+                        oracle_mod.rank2d(img, r, k, drop_bits=b),
+                        brute.rank_dropped_by_coarse_counts(img, r, 2, k, b))
 
 
 def test_reduced_precision(oracle_mod):
