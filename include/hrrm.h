@@ -196,10 +196,19 @@ int32_t hrrm_batch_capacity(void);
  *   wave_slots : 1 = (uniform 2-D trees) the workgroup shares only the first
  *                tier's slot; each wave holds its own slots of deeper subtrees
  *                for the 64 + 2r + 1 columns its windows cover (nslots then
- *                caps the slots per wave); 0 = every slot shared */
+ *                caps the slots per wave); 0 = every slot shared
+ *   window_rows: > 0 = (2-D, full precision) the grey-level-window kernel:
+ *                each wave holds the leaves of 128 consecutive grey levels
+ *                per column of a 64-column strip and skips the tree levels
+ *                above them (Sec. III; adaptive: placed on the medians,
+ *                Sec. III-C), strip segments of window_rows rows; the rows a
+ *                strip cannot finish (byte overflow of a leaf count, medians
+ *                spread wider than the scanned leaves) are recomputed by the
+ *                tiered kernel with the uniform tree's default configuration.
+ *                0 = the tiered kernel alone */
 typedef struct {
   int32_t seg_rows, nslots, min_group, max_groups, lds_budget, tiered_u8, raw_window;
-  int32_t wave_slots;
+  int32_t wave_slots, window_rows;
 } hrrm_tile_config;
 
 /* Set (cfg != NULL) or clear (cfg == NULL) the context's tile configuration

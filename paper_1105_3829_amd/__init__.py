@@ -48,7 +48,8 @@ class TileConfig(ctypes.Structure):
     _fields_ = [("seg_rows", ctypes.c_int32), ("nslots", ctypes.c_int32),
                 ("min_group", ctypes.c_int32), ("max_groups", ctypes.c_int32),
                 ("lds_budget", ctypes.c_int32), ("tiered_u8", ctypes.c_int32),
-                ("raw_window", ctypes.c_int32), ("wave_slots", ctypes.c_int32)]
+                ("raw_window", ctypes.c_int32), ("wave_slots", ctypes.c_int32),
+                ("window_rows", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -25,6 +25,7 @@ ARCH = os.environ.get("HRRM_OFFLOAD_ARCH", "gfx950")
 SOURCES = [
     "median_kernels.hip",
     "median_tiered.hip",
+    "median_window.hip",
     "topology.hip",
     "batched.hip",
     "hrrm_api.cpp",
@@ -36,6 +37,11 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-x", "hip"]
+# Per-source flags.  The grey-level-window kernel's LDS atomics from many lanes
+# to one address (the running lo/hi counts) are left to the LDS unit: the
+# compiler's default rewrite of such atomics into a loop over the active
+# lanes costs more instructions than the hardware takes to serialise them.
+EXTRA = {"median_window.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
 
 
 def hipcc() -> str:
@@ -46,7 +52,7 @@ def hipcc() -> str:
 def _compile(src: str) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + DEVICE + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + DEVICE + COMMON + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

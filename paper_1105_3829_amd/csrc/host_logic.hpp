@@ -151,6 +151,7 @@ inline std::vector<Admitted> plan_admission(Arena& arena,
 struct TuningLine {
   int bytes, dims, r, adaptive;
   int32_t seg_rows, nslots, min_group, max_groups, lds_budget, tiered_u8, raw_window, wave_slots;
+  int32_t window_rows;
   double ms;
 };
 
@@ -174,26 +175,28 @@ inline bool tuning_field(const char* line, const char* name, double* out) {
 // Parses one cache line; false for lines that are not entries or whose values
 // lie outside what a launch accepts (slot count, LDS budget, flags).
 inline bool parse_tuning_line(const char* line, TuningLine* e, int max_slots, int lds_limit) {
-  static const char* const names[13] = {"bytes",     "dims",       "r",          "adaptive",
-                                        "seg_rows",  "nslots",     "min_group",  "max_groups",
-                                        "lds_budget", "tiered_u8", "ms",         "raw_window",
-                                        "wave_slots"};
-  double v[13];
+  static const char* const names[14] = {"bytes",      "dims",       "r",          "adaptive",
+                                        "seg_rows",   "nslots",     "min_group",  "max_groups",
+                                        "lds_budget", "tiered_u8",  "ms",         "raw_window",
+                                        "wave_slots", "window_rows"};
+  double v[14];
   for (int i = 0; i < 11; ++i)
     if (!tuning_field(line, names[i], &v[i])) return false;
   if (!tuning_field(line, names[11], &v[11])) v[11] = 49;
   if (!tuning_field(line, names[12], &v[12])) v[12] = 0;
-  for (int i = 0; i < 13; ++i)
+  if (!tuning_field(line, names[13], &v[13])) v[13] = 0;
+  for (int i = 0; i < 14; ++i)
     if (!(v[i] >= -1e9 && v[i] <= 1e9)) return false;  // also rejects NaN
-  *e = TuningLine{(int)v[0],     (int)v[1],     (int)v[2],     (int)v[3],     (int32_t)v[4],
-                  (int32_t)v[5], (int32_t)v[6], (int32_t)v[7], (int32_t)v[8], (int32_t)v[9],
-                  (int32_t)v[11], (int32_t)v[12], v[10]};
+  *e = TuningLine{(int)v[0],      (int)v[1],      (int)v[2],     (int)v[3],     (int32_t)v[4],
+                  (int32_t)v[5],  (int32_t)v[6],  (int32_t)v[7], (int32_t)v[8], (int32_t)v[9],
+                  (int32_t)v[11], (int32_t)v[12], (int32_t)v[13], v[10]};
   return (e->bytes == 1 || e->bytes == 2) && (e->dims == 2 || e->dims == 3) && e->r >= 0 &&
          e->r <= (e->dims == 2 ? HRRM_MAX_R_2D : HRRM_MAX_R_3D) &&
          (e->adaptive == 0 || e->adaptive == 1) && e->seg_rows >= 1 && e->nslots >= 0 &&
          e->nslots <= max_slots && e->min_group >= 1 && e->max_groups >= 0 &&
          e->lds_budget >= 16 * 1024 && e->lds_budget <= lds_limit && e->raw_window >= 0 &&
-         (e->wave_slots == 0 || e->wave_slots == 1);
+         (e->wave_slots == 0 || e->wave_slots == 1) && e->window_rows >= 0 &&
+         e->window_rows <= (1 << 20);
 }
 
 }  // namespace hrrm

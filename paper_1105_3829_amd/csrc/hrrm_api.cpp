@@ -153,6 +153,14 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     t.max_groups = 1;
     rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
   }
+  // 2-D: the grey-level-window kernel where it measured faster than the
+  // tiered kernel (MI355X; 8-bit low-key 8192^2 r = 8, 16: 0.8-1.1 against
+  // 1.6-1.7 ms; 16-bit X-ray-like 4096^2 r = 8..50), and for every adaptive
+  // 2-D tree from r = 6
+  t.window_rows = 0;
+  if (dims == 2 && ((bytes == 1 && r >= 6 && r <= 16) || (bytes == 2 && r >= 8) ||
+                    (adaptive && r >= 6)))
+    t.window_rows = 64;
   // an image filtered on its own keeps at least two tiles per workgroup slot
   // of the GPU (256 CUs, 1 to 6 workgroups each) when it allows it; in a
   // batch the other images fill the GPU
@@ -204,21 +212,20 @@ int check_variant(int variant, int dtype) {
 
 // ---- launch ------------------------------------------------------------------
 
-int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
-               int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,
-               int64_t rank, int drop, int variant, int dims, hipStream_t stream,
-               const TileConfig* force, const void* est, int64_t est_rs) {
-  const int bytes = dtype == HRRM_U8 ? 1 : 2;
+// Launch arguments of the tiered / dense kernels for tile configuration t;
+// fails when the tile does not fit one launch or the LDS.
+static int tiered_args(const TileConfig& t0, int bytes, int dims, bool adaptive, bool full,
+                       const void* src, void* dst, int64_t w, int64_t h, int64_t d, int64_t srs,
+                       int64_t sss, int64_t drs, int64_t dss, int r, int64_t rank, int drop,
+                       MedianArgs& a, bool& tiered) {
   const int bits = 8 * bytes;
-  const bool adaptive = variant == HRRM_ADAPTIVE;
-  const bool full = variant == HRRM_FULL_UPDATE;  // 8-bit only, checked by the callers
-  TileConfig t = force ? *force : ctx->tile_for(bytes, dims, r, adaptive, w, h, d);
+  TileConfig t = t0;
   if (t.seg_rows <= 0) t.seg_rows = 1;
   t.seg_rows = (int32_t)std::min<int64_t>(t.seg_rows, h);
   // the full update needs every node of every column: dense storage
-  const bool tiered = !full && (bytes == 2 || t.tiered_u8 != 0);
+  tiered = !full && (bytes == 2 || t.tiered_u8 != 0);
 
-  MedianArgs a{};
+  a = MedianArgs{};
   a.src = src;
   a.dst = dst;
   a.w = w;
@@ -245,6 +252,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   const int maxcol = dims == 3 ? (2 * r + 1) * (2 * r + 1) : 2 * r + 1;
   a.mfma = maxcol <= 127 ? 1 : dims == 3 && maxcol <= 255 ? 2 : 0;
   a.topo = nullptr;
+  a.need = nullptr;
 
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;
   if (grid > 0x7fffffff) return fail(HRRM_EUNSUPPORTED, "image too large for one launch");
@@ -281,11 +289,80 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
                                                      a.nslots);
   if (lds > (size_t)kLdsLimit)
     return fail(HRRM_EUNSUPPORTED, "radius %d needs %zu bytes of LDS per workgroup", r, lds);
+  return HRRM_OK;
+}
+
+// 2-D grey-level-window kernel, then the tiered kernel (uniform tree) over the
+// tiles the window kernel flagged.
+static int run_window(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
+                      int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
+                      bool adaptive, hipStream_t stream, uint32_t* need_buf) {
+  // rows the window kernel cannot finish are rare and come alone: short
+  // fallback tiles
+  TileConfig ft = ctx->tile_for(bytes, 2, r, false, w, h, 1);
+  ft.window_rows = 0;
+  ft.seg_rows = 16;
+  MedianArgs fa;
+  bool tiered = true;
+  int rc = tiered_args(ft, bytes, 2, false, false, src, dst, w, h, 1, srs, 0, drs, 0, r, rank, 0,
+                       fa, tiered);
+  if (rc != HRRM_OK) return rc;
+  const int64_t tiles = (int64_t)fa.strips * fa.segs;
+  WindowArgs wa{};
+  wa.src = src;
+  wa.dst = dst;
+  wa.w = w;
+  wa.h = h;
+  wa.srs = srs;
+  wa.drs = drs;
+  wa.rank = rank;
+  wa.r = r;
+  wa.n = (2 * r + 1) * (2 * r + 1);
+  wa.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(t.window_rows, h));
+  wa.strips = (int32_t)((w + 63) / 64);
+  wa.segs = (int32_t)((h + wa.seg_rows - 1) / wa.seg_rows);
+  wa.wave_bytes = (int32_t)window_wave_bytes(r);
+  wa.fb_strips = fa.strips;
+  wa.fb_rows = fa.seg_rows;
+  if ((int64_t)wa.strips * wa.segs > 0x7fffffffLL * 1)
+    return fail(HRRM_EUNSUPPORTED, "image too large for one launch");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  if (!need_buf) {
+    rc = ctx->ensure_need(tiles, stream, &need_buf);
+    if (rc != HRRM_OK) return rc;
+  }
+  wa.need = need_buf;
+  fa.need = need_buf;
+  e = launch_window(wa, bytes, adaptive, stream);
+  if (e != hipSuccess) return fail_hip(e, "window kernel launch");
+  e = launch_median(fa, bytes, 2, false, true, false, stream);
+  if (e != hipSuccess) return fail_hip(e, "median kernel launch");
+  return HRRM_OK;
+}
+
+int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
+               int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,
+               int64_t rank, int drop, int variant, int dims, hipStream_t stream,
+               const TileConfig* force, const void* est, int64_t est_rs) {
+  const int bytes = dtype == HRRM_U8 ? 1 : 2;
+  const bool adaptive = variant == HRRM_ADAPTIVE;
+  const bool full = variant == HRRM_FULL_UPDATE;  // 8-bit only, checked by the callers
+  const TileConfig t = force ? *force : ctx->tile_for(bytes, dims, r, adaptive, w, h, d);
+  if (dims == 2 && drop == 0 && !full && est == nullptr && t.window_rows > 0)
+    return run_window(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, adaptive, stream,
+                      nullptr);
+
+  MedianArgs a;
+  bool tiered = true;
+  int rc = tiered_args(t, bytes, dims, adaptive, full, src, dst, w, h, d, srs, sss, drs, dss, r,
+                       rank, drop, a, tiered);
+  if (rc != HRRM_OK) return rc;
 
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
   if (adaptive) {
-    int rc = ctx->ensure_topology(bytes, w * h * a.d, stream);
+    rc = ctx->ensure_topology(bytes, w * h * a.d, stream);
     if (rc != HRRM_OK) return rc;
     a.topo = (const TopoNode*)ctx->topo;
     e = launch_topology(a, bytes, dims, ctx->topo_ws, (TopoNode*)ctx->topo, stream, est, est_rs);
@@ -293,6 +370,48 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   }
   e = launch_median(a, bytes, dims, adaptive, tiered, full, stream);
   if (e != hipSuccess) return fail_hip(e, "median kernel launch");
+  return HRRM_OK;
+}
+
+int Context::ensure_need(int64_t tiles, hipStream_t stream, uint32_t** out) {
+  NeedBuf* mine = nullptr;
+  NeedBuf* shared = nullptr;
+  for (auto& b : needs) {
+    if (b.stream == stream) mine = &b;
+    if (b.stream == nullptr) shared = &b;
+  }
+  if (mine && mine->count >= (size_t)tiles) {
+    *out = mine->p;
+    return HRRM_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (stream && hipStreamIsCapturing(stream, &cs) == hipSuccess &&
+      cs != hipStreamCaptureStatusNone) {
+    if (!mine && shared && shared->count >= (size_t)tiles) {
+      *out = shared->p;
+      return HRRM_OK;
+    }
+    return fail(HRRM_ENOMEM, "tile flag buffer too small under stream capture "
+                             "(call hrrm_ctx_reserve before capturing)");
+  }
+  if (!mine) {
+    needs.push_back(NeedBuf{stream, nullptr, 0});
+    mine = &needs.back();
+  }
+  if (mine->p) (void)hipFree(mine->p);
+  mine->p = nullptr;
+  mine->count = 0;
+  hipError_t e = hipMalloc(&mine->p, (size_t)tiles * sizeof(uint32_t));
+  if (e != hipSuccess) return fail(HRRM_ENOMEM, "tile flag buffer: %s", hipGetErrorString(e));
+  // every flag starts clear; the tiered kernel clears each flag it consumes
+  e = hipMemsetAsync(mine->p, 0, (size_t)tiles * sizeof(uint32_t), stream);
+  if (e != hipSuccess) return fail_hip(e, "tile flag buffer clear");
+  if (!stream) {
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return fail_hip(e, "tile flag buffer clear");
+  }
+  mine->count = (size_t)tiles;
+  *out = mine->p;
   return HRRM_OK;
 }
 
@@ -333,6 +452,8 @@ Context::~Context() {
   (void)hipSetDevice(device);
   if (topo_ws) (void)hipFree(topo_ws);
   if (topo) (void)hipFree(topo);
+  for (auto& b : needs)
+    if (b.p) (void)hipFree(b.p);
   release_batch();
 }
 
@@ -386,7 +507,17 @@ int hrrm_ctx_reserve(hrrm_ctx ctx, hrrm_dtype dtype, int64_t max_pixels, int32_t
   e = prime_tiered_lds();
   if (e == hipSuccess) e = prime_dense_lds();
   if (e == hipSuccess) e = prime_topology_lds();
+  if (e == hipSuccess) e = prime_window_lds();
   if (e != hipSuccess) return fail_hip(e, "kernel LDS limits");
+  {
+    // flags of the tiered kernel's tiles for any 2-D image of max_pixels
+    // with segments of at least 8 rows (the defaults): ceil(w / 256) *
+    // ceil(h / 8) <= P / 2048 + w / 256 + h / 8 + 1
+    const int64_t tiles = max_pixels / 2048 + max_pixels / 256 + max_pixels / 8 + 2;
+    uint32_t* buf = nullptr;
+    const int rc = c->ensure_need(tiles, nullptr, &buf);
+    if (rc != HRRM_OK) return rc;
+  }
   if (variant == HRRM_ADAPTIVE)
     return c->ensure_topology(dtype == HRRM_U8 ? 1 : 2, max_pixels, nullptr);
   return HRRM_OK;
@@ -466,7 +597,8 @@ static bool tile_ok(const hrrm_tile_config* c) {
   return c->seg_rows >= 1 && c->nslots >= 0 && c->nslots <= kMaxSlots && c->min_group >= 1 &&
          c->min_group <= 65 && c->max_groups >= 0 && c->lds_budget >= 16 * 1024 &&
          c->lds_budget <= kLdsLimit && (c->tiered_u8 == 0 || c->tiered_u8 == 1) &&
-         c->raw_window >= 0 && (c->wave_slots == 0 || c->wave_slots == 1);
+         c->raw_window >= 0 && (c->wave_slots == 0 || c->wave_slots == 1) &&
+         c->window_rows >= 0 && c->window_rows <= (1 << 20);
 }
 
 int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r,
@@ -487,7 +619,8 @@ int hrrm_set_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
   if (cfg) {
     TunedEntry e{bytes, dims, r, ad, TileConfig{cfg->seg_rows, cfg->nslots, cfg->min_group,
                                                 cfg->max_groups, cfg->lds_budget, cfg->tiered_u8,
-                                                cfg->raw_window, cfg->wave_slots},
+                                                cfg->raw_window, cfg->wave_slots,
+                                                cfg->window_rows},
                  0.0};
     v.push_back(e);
   }
@@ -505,7 +638,7 @@ int hrrm_get_tile_config(hrrm_ctx ctx, hrrm_dtype dtype, int32_t dims, int32_t r
   const TileConfig t = c->tile_for(dtype == HRRM_U8 ? 1 : 2, dims, r, variant == HRRM_ADAPTIVE,
                                    width, height, dims == 3 ? depth : 1);
   *out = hrrm_tile_config{t.seg_rows, t.nslots, t.min_group, t.max_groups, t.lds_budget,
-                          t.tiered_u8, t.raw_window, t.wave_slots};
+                          t.tiered_u8, t.raw_window, t.wave_slots, t.window_rows};
   return HRRM_OK;
 }
 

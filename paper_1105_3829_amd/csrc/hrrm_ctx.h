@@ -35,6 +35,17 @@ struct Context {
   void* topo = nullptr;  // TopoNode[2^bits], last entry holds the root index
   size_t topo_bytes = 0;
   std::vector<TunedEntry> tuned;
+  // flags of the tiered kernel's tiles that the grey-level-window kernel
+  // could not finish (all clear between calls), one buffer per stream so that
+  // calls running at the same time on different streams do not share flags;
+  // stream == nullptr: the buffer hrrm_ctx_reserve sizes, also taken by calls
+  // captured on a stream that has no buffer yet
+  struct NeedBuf {
+    hipStream_t stream;
+    uint32_t* p;
+    size_t count;
+  };
+  std::vector<NeedBuf> needs;
 
   // batched launches (persistent kernel), one entry per stream used
   std::vector<BatchStream> batch;
@@ -46,6 +57,9 @@ struct Context {
   // captured); a grown workspace replaces the old one after hipFree, which
   // waits for the device
   int ensure_topology(int bytes, int64_t pixels, hipStream_t stream);
+  // the tile flag buffer of `stream`, grown to `tiles` flags (growing is
+  // refused under capture); *out receives it
+  int ensure_need(int64_t tiles, hipStream_t stream, uint32_t** out);
   void release_batch();
   BatchStream* batch_for(hipStream_t s);
   ~Context();

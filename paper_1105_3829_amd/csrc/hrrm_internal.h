@@ -74,6 +74,9 @@ struct MedianArgs {
   int32_t wpitch;     // columns per wave-private slot (>= 64 + 2r + 1)
   int32_t pad1;
   const TopoNode* topo;  // adaptive topology (device), else null
+  // non-null: recompute only the tiles whose flag is set (flag index = the
+  // tile's workgroup index, 2-D), clearing each flag it consumes
+  uint32_t* need;
 };
 
 // One image of a persistent batched launch: its launch arguments, element size
@@ -95,7 +98,31 @@ struct TileConfig {
   int32_t tiered_u8;  // 1 = tiered storage for u8 as well
   int32_t raw_window; // windows of at most this many values count deeper tiers raw
   int32_t wave_slots; // 1 = deeper subtrees in wave-private slots (uniform 2-D)
+  int32_t window_rows; // > 0: 2-D grey-level-window kernel, strip segments of this many rows
 };
+
+// One launch of the grey-level-window kernel (2-D): strips of 64 output
+// columns x seg_rows rows, one wave each.  A strip segment that cannot finish
+// sets the flags of the tiered kernel's tiles (fb_strips x fb_rows geometry)
+// covering its remaining rows in `need`.
+struct WindowArgs {
+  const void* src;
+  void* dst;
+  int64_t w, h, srs, drs;
+  int64_t rank;
+  int32_t r, n;  // radius, window size (2r+1)^2
+  int32_t seg_rows, strips, segs;
+  int32_t wave_bytes;  // LDS bytes of one wave
+  uint32_t* need;
+  int32_t fb_strips, fb_rows;
+};
+
+size_t window_wave_bytes(int r);
+int window_waves_per_group(int r);
+// adaptive = scanned range placed on the medians (64 leaves); else the uniform
+// tree's pairs of 64-leaf subtrees (128 leaves)
+hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStream_t stream);
+hipError_t prime_window_lds();
 
 // Launch the fused median kernel.  dims = 2 or 3; full = update every node of
 // the window tree at every pixel (8-bit dense storage only).  Returns

@@ -1468,6 +1468,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(WPE))) v
     MedianArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  if (a.need) {  // recompute only flagged tiles, and clear the flag once read
+    if (a.need[bid] == 0u) return;
+    __syncthreads();
+    if (threadIdx.x == 0) a.need[bid] = 0u;
+  }
   const int rest = bid / a.strips;
   tile_body<T, ADAPT, D3, (WPE <= 3), WPS>(a, lds, bid % a.strips, rest % a.segs, rest / a.segs);
 }

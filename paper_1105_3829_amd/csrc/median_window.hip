@@ -1,0 +1,780 @@
+// Grey-level-window running-median kernel for gfx950: 2-D images, 8- and
+// 16-bit data, any rank K.
+//
+// Method: Alekseychuk, "Hierarchical Recursive Running Median" (Sec. III).
+// Column histograms are updated recursively as the window moves down one row
+// (one removal, one insertion per column), the window histogram of a pixel is
+// built from column histograms by the elementary update W(x) = W(x-1) +
+// col(x+r) - col(x-r-1), and the order statistic is found by descending the
+// tree of interval counts: go left when accumulator + left count > K, else
+// add the left count and go right (get_order_statistic).
+//
+// Level skipping.  The medians of neighbouring pixels lie close together
+// (their windows share all but two columns), so the descents of a wave's 64
+// pixels share their top levels.  A wave keeps, per column of its strip,
+// only the leaves of one window of 128 consecutive grey levels [bc, bc+128)
+// as byte counters, plus the number of column values below and above the
+// range of leaves it scans (`lohi`, two 16-bit fields).  For a pixel whose
+// window count below the scanned range (lo) satisfies lo <= K < lo + (count
+// inside), every descent step above the scanned range is fixed - the
+// accumulator after those steps is exactly lo - so the descent starts at
+// the scanned range with accumulator lo and walks its levels, whose node
+// counts are sums of leaf counts.  The scanned range is
+//   * SQ = 32 (uniform tree): the whole 128 leaves [bc, bc+128), bc a
+//     multiple of 64: two neighbouring 6-level subtrees of the uniform tree
+//     (the descent reaches one of them after the skipped levels);
+//   * SQ = 16 (adaptive tree, Sec. III-C): 64 leaves starting anywhere in the
+//     range on a 16-level step, placed where the previous rows' medians lie
+//     (the estimate of the median distribution that shapes the topology):
+//     two short paths to "below" and "above", six levels inside.
+// The range moves with the medians: shifted (SQ = 16) or rebuilt from the
+// raw window (both) when the medians approach its edge, and rebuilt around
+// the exact median of one pixel when a pixel's median falls outside.
+//
+// Exactness.  Window leaf counts are byte fields summed in 32-bit modular
+// arithmetic; the lo/hi fields are exact.  The digit sum of the leaf bytes
+// equals the true count inside the range (N - lo - hi) exactly when no leaf
+// count exceeded 255, so every result is checked; a strip segment whose
+// window counts overflow a byte, or whose medians in one row spread wider
+// than the scanned range, stops and flags its rows for the tiered kernel,
+// which recomputes them (the tiles it covers are flagged in `need`).
+//
+// Work split: one wave per strip of 64 output columns x seg_rows rows, with
+// its own 64 + 2r columns in LDS (no barriers; the waves of a workgroup are
+// independent).  Window counts: every lane reads the bins of the column
+// entering and leaving its window, one DPP prefix sum over the wave per
+// dword turns the differences into running window counts, anchored at the
+// window of the wave's first pixel (`base`, kept up to date by the row steps
+// of its 2r + 1 columns).
+#include "hrrm_internal.h"
+#include "wave.hpp"
+
+namespace hrrm {
+namespace {
+
+constexpr int kBinQ = 32;   // dwords of byte counters per column: 128 grey levels
+constexpr int kPitch = 36;  // dwords per column's counters (36 = 4 mod 32: the
+                            // 128-bit reads of 8 consecutive lanes hit distinct banks)
+constexpr int kLohi = 32;   // dword of the base's lo/hi counts (after its 32 leaf dwords)
+constexpr int kSink = 33;   // pad dword that takes the zero updates of values outside the leaves
+constexpr int kMaxPasses = 6;  // passes over one row before it is left to the tiered kernel
+
+// Where a value goes: leaf dword q with byte increment inc (values outside
+// the 128 leaves: the pad dword kSink, increment 0), and its lo/hi increment
+// relative to the scanned dwords [q0, q0 + sq).
+struct Cls {
+  int q;
+  uint32_t inc, lh;
+};
+
+__device__ __forceinline__ Cls classify(int v, int bc, int q0, int sq) {
+  const int rel = v - bc;
+  const bool in = (uint32_t)rel < 4u * kBinQ;
+  Cls c;
+  c.q = in ? rel >> 2 : kSink;
+  c.inc = in ? 1u << ((rel & 3) << 3) : 0u;
+  // below the scanned dwords (also below the leaves), or above them
+  c.lh = rel < 4 * q0 ? 1u : (rel >= 4 * (q0 + sq) ? 0x10000u : 0u);
+  return c;
+}
+
+__device__ __forceinline__ void lds_add(uint32_t* p, uint32_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t dsum(uint32_t v, uint32_t acc) {
+  return __builtin_amdgcn_sad_u8(v, 0u, acc);  // acc + sum of the four bytes
+}
+
+// One wave's LDS: bins[ncols][kPitch], lohi[ncols], base[kPitch] (the leaf
+// counts of the window of the wave's first pixel; base[kLohi] its lo/hi), then
+// 32 dwords for row16, 16-byte aligned.
+struct WaveLds {
+  uint32_t* bins;
+  uint32_t* lohi;
+  uint32_t* base;
+};
+
+__host__ __device__ constexpr size_t window_base_offset(int ncols) {
+  return (((size_t)ncols * (kPitch + 1) * 4 + 15) & ~(size_t)15);
+}
+
+template <int N>
+using vu = uint32_t __attribute__((ext_vector_type(N)));
+
+// x as a value the compiler cannot see through (emits nothing).
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
+// v[i] among M = 2^k values, i given by its bits from the most significant
+// (the first descent decision) down: one two-way select per value and level.
+// Both candidates of every select pass through opaque(): a select between two
+// elements of one vector (or array) is otherwise turned into a read at a
+// computed index, lowered to a compare and a select per element (or, for an
+// array in memory, a scratch-memory load).
+template <int M>
+__device__ __forceinline__ uint32_t pick(vu<M> v, bool msb) {
+  static_assert(M == 2, "one bit selects between two values");
+  const uint32_t lo = opaque(v[0]), hi = opaque(v[1]);
+  return msb ? hi : lo;
+}
+template <int M, typename... B>
+__device__ __forceinline__ uint32_t pick(vu<M> v, bool msb, bool next, B... rest) {
+  vu<M / 2> h;
+#pragma unroll
+  for (int k = 0; k < M / 2; ++k) {
+    const uint32_t lo = opaque(v[k]), hi = opaque(v[M / 2 + k]);
+    h[k] = msb ? hi : lo;
+  }
+  return pick<M / 2>(h, next, rest...);
+}
+
+// Pairwise sums out[k] = v[2k] + v[2k + 1] (counts of the parent nodes).
+template <int M>
+__device__ __forceinline__ vu<M / 2> pairs(vu<M> v) {
+  vu<M / 2> o;
+#pragma unroll
+  for (int k = 0; k < M / 2; ++k) o[k] = v[2 * k] + v[2 * k + 1];
+  return o;
+}
+
+// Even elements out[k] = v[2k]: the left children of the next level's nodes.
+template <int M>
+__device__ __forceinline__ vu<M / 2> evens(vu<M> v) {
+  vu<M / 2> o;
+#pragma unroll
+  for (int k = 0; k < M / 2; ++k) o[k] = v[2 * k];
+  return o;
+}
+
+// One step of get_order_statistic: left-child count c; the remaining rank k
+// goes right (and drops c) when it reaches c.
+__device__ __forceinline__ bool step(uint32_t c, uint32_t& k) {
+  const bool rt = k >= c;
+  k -= rt ? c : 0u;
+  return rt;
+}
+
+// Window counts of the scanned range for every lane's pixel: W[k] = leaf
+// bytes of dword q0 + k, wl = lo | hi << 16.  All 64 lanes active.
+template <int SQ>
+__device__ __forceinline__ vu<SQ> window_counts(const WaveLds& L, int q0, int lane, int r2,
+                                                uint32_t& wl) {
+  const int ci = lane + r2;                  // column x + r
+  const int co = lane == 0 ? ci : lane - 1;  // column x - r - 1 (lane 0: none)
+  const uint32_t* pi = L.bins + ci * kPitch + q0;
+  const uint32_t* po = L.bins + co * kPitch + q0;
+  const uint32_t* pb = L.base + q0;
+  vu<SQ> W;
+#pragma unroll
+  for (int k = 0; k < SQ; k += 4) {
+    const uint4 a = *(const uint4*)(pi + k);
+    const uint4 b = *(const uint4*)(po + k);
+    const uint4 c = *(const uint4*)(pb + k);
+    W[k] = c.x + wave_scan(a.x - b.x);
+    W[k + 1] = c.y + wave_scan(a.y - b.y);
+    W[k + 2] = c.z + wave_scan(a.z - b.z);
+    W[k + 3] = c.w + wave_scan(a.w - b.w);
+  }
+  wl = L.base[kLohi] + wave_scan(L.lohi[ci] - L.lohi[co]);
+  return W;
+}
+
+// Descent over the 4*SQ leaves from accumulator lo (kp = K - lo): returns the
+// leaf offset of the K-th value; ok = the order statistic lies in the
+// scanned range and no leaf count overflowed a byte.
+template <int SQ>
+__device__ __forceinline__ int descend(vu<SQ> W, int kp, int win, bool& ok) {
+  // node counts of the dword-level tree: t0 per dword (4 leaves), t1 per
+  // pair of dwords, t2 per four, t3 per eight (32 leaves)
+  vu<SQ> t0;
+#pragma unroll
+  for (int k = 0; k < SQ; ++k) t0[k] = dsum(W[k], 0u);
+  const vu<SQ / 2> t1 = pairs<SQ>(t0);
+  const vu<SQ / 4> t2 = pairs<SQ / 2>(t1);
+  const vu<SQ / 8> t3 = pairs<SQ / 4>(t2);
+  uint32_t total = 0;
+#pragma unroll
+  for (int k = 0; k < SQ / 8; ++k) total += t3[k];
+  ok = kp >= 0 && kp < win && (int)total == win;
+  uint32_t k = (uint32_t)kp;
+  int off;
+  if constexpr (SQ == 16) {
+    const bool b1 = step(t3[0], k);
+    const bool b2 = step(pick<2>(evens<4>(t2), b1), k);
+    const bool b3 = step(pick<4>(evens<8>(t1), b1, b2), k);
+    const bool b4 = step(pick<8>(evens<16>(t0), b1, b2, b3), k);
+    const uint32_t d = pick<16>(W, b1, b2, b3, b4);
+    const bool b5 = step((d & 0xffu) + ((d >> 8) & 0xffu), k);
+    const bool b6 = step((d >> (b5 ? 16 : 0)) & 0xffu, k);
+    off = (b1 ? 32 : 0) + (b2 ? 16 : 0) + (b3 ? 8 : 0) + (b4 ? 4 : 0) + (b5 ? 2 : 0) + (b6 ? 1 : 0);
+  } else {
+    const bool b0 = step(t3[0] + t3[1], k);
+    const bool b1 = step(pick<2>(evens<4>(t3), b0), k);
+    const bool b2 = step(pick<4>(evens<8>(t2), b0, b1), k);
+    const bool b3 = step(pick<8>(evens<16>(t1), b0, b1, b2), k);
+    const bool b4 = step(pick<16>(evens<32>(t0), b0, b1, b2, b3), k);
+    const uint32_t d = pick<32>(W, b0, b1, b2, b3, b4);
+    const bool b5 = step((d & 0xffu) + ((d >> 8) & 0xffu), k);
+    const bool b6 = step((d >> (b5 ? 16 : 0)) & 0xffu, k);
+    off = (b0 ? 64 : 0) + (b1 ? 32 : 0) + (b2 ? 16 : 0) + (b3 ? 8 : 0) + (b4 ? 4 : 0) +
+          (b5 ? 2 : 0) + (b6 ? 1 : 0);
+  }
+  return off;
+}
+
+// Exact rank-K value of the clamp-to-edge window of pixel (xc, yc), by two
+// 256-bin histograms (high byte, then low byte among values with that high
+// byte; 8-bit data: one).  hist: 256 dwords of the wave's LDS.
+template <typename T>
+__device__ __forceinline__ int window_rank_exact(const T* __restrict__ src, int64_t srs, int64_t w, int64_t h,
+                                 int64_t xc, int64_t yc, int r, int rank, uint32_t* hist,
+                                 int lane) {
+  constexpr int kPasses = sizeof(T) == 2 ? 2 : 1;
+  constexpr int kB = 16;  // window rows loaded before any is counted
+  int k = rank, prefix = 0;
+  for (int pass = 0; pass < kPasses; ++pass) {
+    *(uint4*)(hist + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
+    __builtin_amdgcn_wave_barrier();
+    for (int dx0 = -r; dx0 <= r; dx0 += 64) {
+      const int dx = dx0 + lane;
+      const int64_t col = clampi(xc + dx, w - 1);
+      for (int dy0 = -r; dy0 <= r; dy0 += kB) {
+        int v[kB];
+#pragma unroll
+        for (int t = 0; t < kB; ++t) v[t] = (int)src[clampi(yc + dy0 + t, h - 1) * srs + col];
+#pragma unroll
+        for (int t = 0; t < kB; ++t) {
+          if (dx <= r && dy0 + t <= r) {
+            if (kPasses == 1) {
+              lds_add(hist + v[t], 1u);
+            } else if (pass == 0) {
+              lds_add(hist + (v[t] >> 8), 1u);
+            } else if ((v[t] >> 8) == prefix) {
+              lds_add(hist + (v[t] & 255), 1u);
+            }
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const uint4 hb = *(const uint4*)(hist + 4 * lane);
+    const uint32_t s = hb.x + hb.y + hb.z + hb.w;
+    const uint32_t inc = wave_scan(s), exc = inc - s;
+    const bool mine = exc <= (uint32_t)k && (uint32_t)k < inc;
+    int bin = 4 * lane;
+    uint32_t below = exc;
+    if ((uint32_t)k >= below + hb.x) {
+      below += hb.x;
+      ++bin;
+      if ((uint32_t)k >= below + hb.y) {
+        below += hb.y;
+        ++bin;
+        if ((uint32_t)k >= below + hb.z) {
+          below += hb.z;
+          ++bin;
+        }
+      }
+    }
+    const uint64_t bm = ballot(mine);
+    const int L = bm ? (int)__builtin_ctzll(bm) : 0;
+    bin = readlane(bin, L);
+    k -= readlane((int)below, L);
+    prefix = kPasses == 2 && pass == 0 ? bin : (prefix << 8) | bin;
+    __builtin_amdgcn_wave_barrier();
+  }
+  return prefix;
+}
+
+
+// Rebuild every held column's counters, and the base, for the window of row
+// y from the raw values: zero, insert the 2r + 1 clamped rows of each column,
+// then base = sum of columns 0..2r.  Values are loaded eight rows at a time
+// before any is inserted, so their latencies overlap.
+template <typename T, int KC>
+__device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, int h, int r,
+                                        const int (&gx)[KC], int ncols, const WaveLds& L,
+                                        int wave_dwords, int y, int bc, int q0, int sq,
+                                        int lane) {
+  uint4* z = (uint4*)L.bins;
+  for (int i = lane; i < wave_dwords / 4; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
+  __builtin_amdgcn_wave_barrier();
+  constexpr int kBatch = 8;
+  for (int j0 = -r; j0 <= r; j0 += kBatch) {
+    const T* rows[kBatch];
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+      const int yy = y + j0 + t;
+      rows[t] = src + (int64_t)(yy < 0 ? 0 : (yy > h - 1 ? h - 1 : yy)) * srs;
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = lane + 64 * k;
+      if (c < ncols) {
+        int v[kBatch];
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) v[t] = (int)rows[t][gx[k]];
+#pragma unroll
+        for (int t = 0; t < kBatch; ++t) {
+          if (j0 + t <= r) {
+            const Cls cl = classify(v[t], bc, q0, sq);
+            lds_add(L.bins + c * kPitch + cl.q, cl.inc);
+            lds_add(L.lohi + c, cl.lh);
+          }
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane <= kBinQ) {
+    uint32_t s = 0;
+    if (lane < kBinQ) {
+      for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * kPitch + lane];
+    } else {
+      for (int c = 0; c <= 2 * r; ++c) s += L.lohi[c];
+    }
+    L.base[lane] = s;  // lane kBinQ writes base[kLohi]
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Move the scanned dwords from [q0, q0 + s0) to [q1, q1 + s1): every column's
+// lo/hi gains or loses the leaves crossing the edges (column leaf bytes are
+// exact: at most 2r + 1 <= 255 values), then the base's lo/hi is summed again
+// from the columns.  All 64 lanes active.
+template <int KC>
+__device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, int q0, int s0,
+                                         int q1, int s1, int lane) {
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+    if (c < ncols) {
+      const uint32_t* col = L.bins + c * kPitch;
+      uint32_t d = 0;  // lo gain + (hi gain << 16), modulo 2^32
+#pragma unroll
+      for (int q = 0; q < kBinQ; q += 4) {
+        const uint4 u = *(const uint4*)(col + q);
+        const uint32_t e[4] = {dsum(u.x, 0u), dsum(u.y, 0u), dsum(u.z, 0u), dsum(u.w, 0u)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int qq = q + i;
+          const int lo = (qq < q1 ? 1 : 0) - (qq < q0 ? 1 : 0);
+          const int hi = (qq >= q1 + s1 ? 1 : 0) - (qq >= q0 + s0 ? 1 : 0);
+          d += (uint32_t)(lo + (hi << 16)) * e[i];
+        }
+      }
+      lds_add(L.lohi + c, d);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int c = lane + 64 * k;
+    if (c <= r2) s += L.lohi[c];
+  }
+  s = wave_scan(s);
+  if (lane == 63) L.base[kLohi] = s;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// One pass over a row with the current range: every lane's leaf offset and
+// whether its check passed; over the live lanes, the lanes whose order
+// statistic lies below / above the scanned leaves.
+struct RowOut {
+  int off, lo;
+  bool ok;
+  uint64_t low, high;
+};
+
+template <int SQ>
+__device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane, int r2, int n,
+                                              int rank, bool live) {
+  uint32_t wl;
+  const vu<SQ> W = window_counts<SQ>(L, q0, lane, r2, wl);
+  const int lo = (int)(wl & 0xffffu), hi = (int)(wl >> 16);
+  const int win = n - lo - hi;
+  const int kp = rank - lo;
+  RowOut o;
+  o.lo = lo;
+  o.off = descend<SQ>(W, kp, win, o.ok);
+  o.low = ballot(live && kp < 0);
+  o.high = ballot(live && kp >= win);
+  return o;
+}
+
+// Exact window counts of the 64 leaves in dwords [qs, qs + 16) with 16-bit
+// fields, for rows where a leaf count passed 255 (a value repeated that often
+// in one window: clamp-to-edge repeats a corner pixel (r+1)^2 times).
+// `below` is each pixel's exact window count below these leaves.  Per lane:
+// ok = its order statistic lies in these leaves, off its leaf offset, cnt the
+// exact number of window values in these leaves.  b16: 32 dwords of the
+// wave's LDS for the 16-bit counts of the wave's first window.  All 64 lanes
+// active.
+__device__ __forceinline__ void row16(const WaveLds& L, uint32_t* b16, int qs, int lane, int r2,
+                                      int rank, int below, int& off, bool& ok, int& cnt) {
+  // the first window's counts, summed again from its 2r + 1 columns
+  if (lane < 32) {
+    uint32_t acc = 0;
+    const int q = qs + (lane >> 1), sh = (lane & 1) * 8;
+    for (int c = 0; c <= r2; ++c) acc += (L.bins[c * kPitch + q] >> sh) & 0x00ff00ffu;
+    b16[lane] = acc;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int ci = lane + r2;
+  const int co = lane == 0 ? ci : lane - 1;
+  const uint32_t* pi = L.bins + ci * kPitch + qs;
+  const uint32_t* po = L.bins + co * kPitch + qs;
+  // F[2q]: leaves 4q and 4q + 2, F[2q + 1]: leaves 4q + 1 and 4q + 3
+  vu<32> F;
+#pragma unroll
+  for (int k = 0; k < 16; k += 4) {
+    const uint4 a = *(const uint4*)(pi + k);
+    const uint4 b = *(const uint4*)(po + k);
+    const uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = k + i;
+      F[2 * q] = b16[2 * q] + wave_scan((av[i] & 0x00ff00ffu) - (bv[i] & 0x00ff00ffu));
+      F[2 * q + 1] =
+          b16[2 * q + 1] + wave_scan(((av[i] >> 8) & 0x00ff00ffu) - ((bv[i] >> 8) & 0x00ff00ffu));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  vu<16> t0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    t0[q] = (F[2 * q] & 0xffffu) + (F[2 * q] >> 16) + (F[2 * q + 1] & 0xffffu) +
+            (F[2 * q + 1] >> 16);
+  const vu<8> t1 = pairs<16>(t0);
+  const vu<4> t2 = pairs<8>(t1);
+  const vu<2> t3 = pairs<4>(t2);
+  cnt = (int)(t3[0] + t3[1]);
+  const int kp = rank - below;
+  ok = kp >= 0 && kp < cnt;
+  uint32_t k = (uint32_t)kp;
+  const bool b1 = step(t3[0], k);
+  const bool b2 = step(pick<2>(evens<4>(t2), b1), k);
+  const bool b3 = step(pick<4>(evens<8>(t1), b1, b2), k);
+  const bool b4 = step(pick<8>(evens<16>(t0), b1, b2, b3), k);
+  vu<16> lo, hi;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    lo[q] = F[2 * q];
+    hi[q] = F[2 * q + 1];
+  }
+  const uint32_t fl = pick<16>(lo, b1, b2, b3, b4), fh = pick<16>(hi, b1, b2, b3, b4);
+  const bool b5 = step((fl & 0xffffu) + (fh & 0xffffu), k);
+  const bool b6 = step(b5 ? fl >> 16 : fl & 0xffffu, k);
+  off = (b1 ? 32 : 0) + (b2 ? 16 : 0) + (b3 ? 8 : 0) + (b4 ? 4 : 0) + (b5 ? 2 : 0) + (b6 ? 1 : 0);
+}
+
+template <typename T, bool ADAPT, int KC, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WPG + wv;
+  if (tile >= (int64_t)a.strips * a.segs) return;
+  const int strip = (int)(tile % a.strips), seg = (int)(tile / a.strips);
+  const T* __restrict__ src = (const T*)a.src;
+  T* __restrict__ dst = (T*)a.dst;
+  const int r = a.r, r2 = 2 * a.r, ncols = 64 + 2 * a.r;
+  const int w = (int)a.w, h = (int)a.h;
+  const int x0 = strip * 64;
+  int gx[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int x = x0 - r + lane + 64 * k;
+    gx[k] = x < 0 ? 0 : (x > w - 1 ? w - 1 : x);
+  }
+
+  WaveLds L;
+  L.bins = (uint32_t*)(lds + (size_t)wv * a.wave_bytes);
+  L.lohi = L.bins + (size_t)ncols * kPitch;
+  L.base = (uint32_t*)(lds + (size_t)wv * a.wave_bytes + window_base_offset(ncols));
+  const int wave_dwords = a.wave_bytes / 4;
+
+  const int y0 = seg * a.seg_rows;
+  const int y1 = y0 + a.seg_rows < h ? y0 + a.seg_rows : h;
+  const bool live = x0 + lane < w;
+  constexpr int maxv = sizeof(T) == 2 ? 65535 : 255;
+  const int rank = (int)a.rank;
+
+  // scanned range: dwords [q0, q0 + sq) of the leaves [bc, bc + 128);
+  // adaptive trees scan 16 dwords placed on the medians, widening to all 32
+  // for rows whose medians spread wider; the uniform tree scans all 32
+  int bc = 0, q0 = 0;
+  bool wide = !ADAPT;
+  auto place = [&](int m) {
+    if (!ADAPT) {  // two 64-leaf subtrees of the uniform tree, m in the middle half
+      bc = (m & ~63) - ((m & 63) < 32 ? 64 : 0);
+      bc = bc < 0 ? 0 : bc;
+      q0 = 0;
+    } else if (wide) {
+      bc = (m - 64) & ~15;
+      bc = bc < 0 ? 0 : bc;
+      q0 = 0;
+    } else {  // 64 scanned leaves centred on m, inside the 128 leaves
+      int bs = (m - 32 + 8) & ~15;
+      bs = bs < 0 ? 0 : bs;
+      bc = bs - 32 < 0 ? 0 : bs - 32;
+      q0 = (bs - bc) >> 2;
+    }
+  };
+  auto sq = [&]() { return wide ? kBinQ : 16; };
+  auto estimate = [&](int lane_of, int y) -> int {
+    const int xc = x0 + lane_of < w ? x0 + lane_of : w - 1;
+    return window_rank_exact<T>(src, a.srs, a.w, a.h, xc, y, r, rank, L.bins, lane);
+  };
+  auto build = [&](int y) {
+    rebuild<T, KC>(src, a.srs, h, r, gx, ncols, L, wave_dwords, y, bc, q0, sq(), lane);
+  };
+  // a row this strip cannot finish: flag the tiered kernel's tile holding it
+  // (that tile is recomputed whole after this launch)
+  auto flag_row = [&](int y) {
+    if (lane == 0) a.need[(int64_t)(y / a.fb_rows) * a.fb_strips + x0 / kBlock] = 1u;
+  };
+
+  place(estimate(32, y0));
+  build(y0);
+
+  for (int y = y0; y < y1; ++y) {
+    // raw values of the next row step, loaded before they are needed
+    int vo[KC], vi[KC];
+    {
+      const int yo = y - r < 0 ? 0 : (y - r > h - 1 ? h - 1 : y - r);
+      const int yi = y + r + 1 > h - 1 ? h - 1 : y + r + 1;
+      const T* ro = src + (int64_t)yo * a.srs;
+      const T* ri = src + (int64_t)yi * a.srs;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        vo[k] = (int)ro[gx[k]];
+        vi[k] = (int)ri[gx[k]];
+      }
+    }
+    // passes over the row until every live pixel has its result: a range
+    // that misses some medians moves (adaptive: first to all 128 leaves;
+    // uniform: by one subtree) or is rebuilt around the exact median of the
+    // first pixel still open; results already found stay
+    int res = 0;
+    bool have = false, done = true;
+    for (int tries = 0;; ++tries) {
+      RowOut o;
+      if (ADAPT && !wide)
+        o = row_medians<16>(L, q0, lane, r2, a.n, rank, live);
+      else
+        o = row_medians<kBinQ>(L, q0, lane, r2, a.n, rank, live);
+      if (!have && o.ok) {
+        res = bc + 4 * q0 + o.off;
+        have = true;
+      }
+      uint64_t open = ballot(live && !have);
+      if (!open) break;
+      if (open & ~(o.low | o.high)) {
+        // a leaf count passed 255: count the scanned leaves again with
+        // 16-bit fields, 64 leaves at a time
+        int below = o.lo;
+        for (int qs = q0; qs < q0 + (ADAPT && !wide ? 16 : kBinQ); qs += 16) {
+          int off16, cnt16;
+          bool ok16;
+          row16(L, L.base + kPitch, qs, lane, r2, rank, below, off16, ok16, cnt16);
+          if (!have && ok16) {
+            res = bc + 4 * qs + off16;
+            have = true;
+          }
+          below += cnt16;
+        }
+        open = ballot(live && !have);
+        if (!open) break;
+      }
+      // a count that still disagrees, or too many passes: the tiered kernel
+      // takes this row
+      if ((open & ~(o.low | o.high)) || tries >= kMaxPasses) {
+        done = false;
+        break;
+      }
+      if (ADAPT && !wide) {  // scan all 128 leaves
+        retarget<KC>(L, ncols, r2, q0, 16, 0, kBinQ, lane);
+        q0 = 0;
+        wide = true;
+        continue;
+      }
+      const uint64_t lo = o.low & open, hi = o.high & open;
+      if (!ADAPT && tries == 0 && !(lo && hi)) {  // move the pair of subtrees by one
+        const int nbc = bc + (lo ? -64 : 64);
+        if (nbc >= 0 && nbc <= maxv) {
+          bc = nbc;
+          build(y);
+          continue;
+        }
+      }
+      place(estimate((int)__builtin_ctzll(open), y));
+      build(y);
+    }
+    if (!done) {
+      // leave the rest of the fallback tile to the tiered kernel and start
+      // again at the next one
+      flag_row(y);
+      const int ny = (y / a.fb_rows + 1) * a.fb_rows;
+      if (ny >= y1) return;
+      y = ny - 1;
+      place(estimate(32, ny));
+      build(ny);
+      continue;
+    }
+    if (live) dst[(int64_t)y * a.drs + x0 + lane] = (T)res;
+    if (y + 1 >= y1) break;
+    const int off = res - (bc + 4 * q0);  // relative to the current scanned leaves
+
+    // keep the medians away from the edges of the scanned leaves
+    constexpr int kMargin = 8;
+    bool rebuilt = false;
+    if (ADAPT && wide) {
+      // back to 16 scanned dwords once the row's medians fit them with margins
+      int q1 = -1;
+#pragma unroll
+      for (int q = 0; q <= kBinQ - 16; q += 4)
+        if (q1 < 0 && !ballot(live && (off < 4 * q + kMargin || off >= 4 * q + 64 - kMargin)))
+          q1 = q;
+      if (q1 >= 0) {
+        retarget<KC>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
+        q0 = q1;
+        wide = false;
+      }
+    } else if (ADAPT) {
+      const int bs = bc + 4 * q0;
+      const bool near_lo = ballot(live && off < kMargin) != 0;
+      const bool near_hi = ballot(live && off >= 64 - kMargin) != 0;
+      // shift by 16 leaves when the far side keeps its margin afterwards
+      const bool room_lo = ballot(live && off >= 64 - kMargin - 16) == 0;
+      const bool room_hi = ballot(live && off < kMargin + 16) == 0;
+      if (near_lo && room_lo && bs > 0) {
+        if (q0 >= 4) {
+          retarget<KC>(L, ncols, r2, q0, 16, q0 - 4, 16, lane);
+          q0 -= 4;
+        } else {
+          place(bs + 32 - 16);
+          build(y + 1);
+          rebuilt = true;
+        }
+      } else if (near_hi && room_hi && bs + 64 <= maxv) {
+        if (q0 + 4 <= kBinQ - 16) {
+          retarget<KC>(L, ncols, r2, q0, 16, q0 + 4, 16, lane);
+          q0 += 4;
+        } else {
+          place(bs + 32 + 16);
+          build(y + 1);
+          rebuilt = true;
+        }
+      }
+    } else {
+      // move the pair of subtrees by one subtree
+      const bool near_lo = ballot(live && off < kMargin) != 0;
+      const bool near_hi = ballot(live && off >= 4 * kBinQ - kMargin) != 0;
+      const bool room_lo = ballot(live && off >= 64 - kMargin) == 0;
+      const bool room_hi = ballot(live && off < 64 + kMargin) == 0;
+      if ((near_lo && room_lo && bc >= 64) || (near_hi && room_hi && bc + 128 <= maxv)) {
+        bc += near_lo ? -64 : 64;
+        build(y + 1);
+        rebuilt = true;
+      }
+    }
+    if (rebuilt) continue;
+
+    // row step y -> y + 1: remove row y - r, insert row y + r + 1 (clamped);
+    // a removal and an insertion in one dword are one update
+    const int s = sq();
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int c = lane + 64 * k;
+      if (c < ncols) {
+        const Cls o = classify(vo[k], bc, q0, s);
+        const Cls i = classify(vi[k], bc, q0, s);
+        const bool same = i.q == o.q;
+        const uint32_t di = same ? i.inc - o.inc : i.inc;
+        const uint32_t dl = i.lh - o.lh;
+        uint32_t* col = L.bins + c * kPitch;
+        lds_add(col + i.q, di);
+        lds_add(col + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
+        lds_add(L.lohi + c, dl);
+        if (c <= r2) {
+          lds_add(L.base + i.q, di);
+          lds_add(L.base + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
+          lds_add(L.base + kLohi, dl);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Columns one lane holds: ceil((64 + 2r) / 64).
+constexpr int kc_for(int r) { return (64 + 2 * r + 63) / 64; }
+
+template <typename T, bool ADAPT, int KC, int WPG>
+hipError_t launch_k(const WindowArgs& a, hipStream_t stream) {
+  const size_t lds = (size_t)WPG * a.wave_bytes;
+  const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG>;
+  hipError_t e = ensure_dynamic_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  const int64_t grid = ((int64_t)a.strips * a.segs + WPG - 1) / WPG;
+  hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG>), dim3((uint32_t)grid), dim3(64 * WPG),
+                     lds, stream, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool ADAPT>
+hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
+  const int kc = kc_for(a.r);
+  const int wpg = window_waves_per_group(a.r);
+  if (kc <= 2) return launch_k<T, ADAPT, 2, 4>(a, stream);  // r <= 32
+  if (kc == 3) return wpg >= 4 ? launch_k<T, ADAPT, 3, 4>(a, stream)
+                               : launch_k<T, ADAPT, 3, 2>(a, stream);
+  return wpg >= 2 ? launch_k<T, ADAPT, 5, 2>(a, stream) : launch_k<T, ADAPT, 5, 1>(a, stream);
+}
+
+template <typename T, bool ADAPT>
+hipError_t prime_w() {
+  const void* ks[] = {(const void*)k_median_window<T, ADAPT, 2, 4>,
+                      (const void*)k_median_window<T, ADAPT, 3, 4>,
+                      (const void*)k_median_window<T, ADAPT, 3, 2>,
+                      (const void*)k_median_window<T, ADAPT, 5, 2>,
+                      (const void*)k_median_window<T, ADAPT, 5, 1>};
+  for (const void* k : ks) {
+    const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+size_t window_wave_bytes(int r) {
+  const int ncols = 64 + 2 * r;
+  // + base (kPitch dwords) + the 16-bit counts of the first window (32)
+  return window_base_offset(ncols) + (size_t)(kPitch + 32) * 4;
+}
+
+int window_waves_per_group(int r) {
+  const size_t b = window_wave_bytes(r);
+  return 4 * b <= (size_t)kLdsLimit ? 4 : 2 * b <= (size_t)kLdsLimit ? 2 : 1;
+}
+
+hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStream_t stream) {
+  if (bytes == 1)
+    return adaptive ? launch_w<uint8_t, true>(a, stream) : launch_w<uint8_t, false>(a, stream);
+  return adaptive ? launch_w<uint16_t, true>(a, stream) : launch_w<uint16_t, false>(a, stream);
+}
+
+hipError_t prime_window_lds() {
+  hipError_t e = prime_w<uint8_t, true>();
+  if (e == hipSuccess) e = prime_w<uint8_t, false>();
+  if (e == hipSuccess) e = prime_w<uint16_t, true>();
+  if (e == hipSuccess) e = prime_w<uint16_t, false>();
+  return e;
+}
+
+}  // namespace hrrm

@@ -83,10 +83,11 @@ int save_tuning(const Context* c, const char* path) {
     fprintf(f,
             " {\"bytes\": %d, \"dims\": %d, \"r\": %d, \"adaptive\": %d, \"seg_rows\": %d, "
             "\"nslots\": %d, \"min_group\": %d, \"max_groups\": %d, \"lds_budget\": %d, "
-            "\"tiered_u8\": %d, \"raw_window\": %d, \"wave_slots\": %d, \"ms\": %.5f}%s\n",
+            "\"tiered_u8\": %d, \"raw_window\": %d, \"wave_slots\": %d, \"window_rows\": %d, "
+            "\"ms\": %.5f}%s\n",
             e.bytes, e.dims, e.r, e.adaptive, e.cfg.seg_rows, e.cfg.nslots, e.cfg.min_group,
             e.cfg.max_groups, e.cfg.lds_budget, e.cfg.tiered_u8, e.cfg.raw_window,
-            e.cfg.wave_slots, e.ms, i + 1 < c->tuned.size() ? "," : "");
+            e.cfg.wave_slots, e.cfg.window_rows, e.ms, i + 1 < c->tuned.size() ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -103,7 +104,8 @@ int load_tuning(Context* c, const char* path) {
     if (!parse_tuning_line(line, &t, kMaxSlots, kLdsLimit)) continue;
     got.push_back(TunedEntry{t.bytes, t.dims, t.r, t.adaptive,
                              TileConfig{t.seg_rows, t.nslots, t.min_group, t.max_groups,
-                                        t.lds_budget, t.tiered_u8, t.raw_window, t.wave_slots},
+                                        t.lds_budget, t.tiered_u8, t.raw_window, t.wave_slots,
+                                        t.window_rows},
                              t.ms});
   }
   fclose(f);
@@ -196,12 +198,14 @@ int autotune(Context* c, const void* d_sample, int dtype, int r, int variant, in
     if (bytes == 1) axes.push_back({5, {0, 1}});                          // tiered_u8
     axes.push_back({6, {0, 9, 27, 49, 81}});                              // raw_window
     if (!adaptive) axes.push_back({7, {0, 1}});                           // wave_slots
+    axes.push_back({8, {0, 32, 64, 128}});                                // window_rows
     for (int pass = 0; pass < 2; ++pass) {
       for (auto& ax : axes) {
         for (int v : ax.second) {
           TileConfig t = cur;
-          int32_t* f[8] = {&t.seg_rows,   &t.nslots,    &t.min_group,  &t.max_groups,
-                           &t.lds_budget, &t.tiered_u8, &t.raw_window, &t.wave_slots};
+          int32_t* f[9] = {&t.seg_rows,   &t.nslots,     &t.min_group,  &t.max_groups,
+                           &t.lds_budget, &t.tiered_u8,  &t.raw_window, &t.wave_slots,
+                           &t.window_rows};
           if (*f[ax.first] == v) continue;
           *f[ax.first] = v;
           if (ax.first == 5 && v == 1 && t.max_groups > 8) t.max_groups = 1;
