@@ -112,6 +112,13 @@ struct WindowArgs {
   int64_t rank;
   int32_t r, n;  // radius, window size (2r+1)^2
   int32_t seg_rows, strips, segs;
+  // Tiles near the image's edges, whose windows are dominated by a repeated
+  // edge column or row (so that their medians stray from their neighbours'),
+  // run first, in short segments of border_rows rows: the first and last
+  // strip over all rows (side_tiles tiles), then the other strips' rows
+  // [0, top_end) (top_tiles tiles) and [bot_start, h); the rest of those
+  // strips, rows [top_end, bot_start), follows in segments of seg_rows rows.
+  int32_t border_rows, border_tiles, side_tiles, top_tiles, top_end, bot_start;
   int32_t wave_bytes;  // LDS bytes of one wave
   uint32_t* need;
   int32_t fb_strips, fb_rows;

@@ -291,7 +291,7 @@ __device__ __forceinline__ int window_rank_exact(const T* __restrict__ src, int6
 
 // Rebuild every held column's counters, and the base, for the window of row
 // y from the raw values: zero, insert the 2r + 1 clamped rows of each column,
-// then base = sum of columns 0..2r.  Values are loaded eight rows at a time
+// then base = sum of columns 0..2r.  Values are loaded sixteen rows at a time
 // before any is inserted, so their latencies overlap.
 template <typename T, int KC>
 __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, int h, int r,
@@ -301,7 +301,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
   uint4* z = (uint4*)L.bins;
   for (int i = lane; i < wave_dwords / 4; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
   __builtin_amdgcn_wave_barrier();
-  constexpr int kBatch = 8;
+  constexpr int kBatch = 16;
   for (int j0 = -r; j0 <= r; j0 += kBatch) {
     const T* rows[kBatch];
 #pragma unroll
@@ -476,9 +476,35 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WPG + wv;
-  if (tile >= (int64_t)a.strips * a.segs) return;
-  const int strip = (int)(tile % a.strips), seg = (int)(tile / a.strips);
+  // tiles in launch order: short segments near the image's edges first (see
+  // WindowArgs), then the inner strips' segments, neighbouring strips together
+  const int64_t tile = (int64_t)blockIdx.x * WPG + wv;
+  const int inner = a.strips > 2 ? a.strips - 2 : 0;
+  const int64_t mid_tiles =
+      inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0;
+  if (tile >= (int64_t)a.border_tiles + mid_tiles) return;
+  int strip, y0, y1;
+  if (tile < a.side_tiles) {
+    const int sides = a.strips > 1 ? 2 : 1;
+    strip = (int)(tile % sides) ? a.strips - 1 : 0;
+    y0 = (int)(tile / sides) * a.border_rows;
+    y1 = y0 + a.border_rows;
+  } else if (tile < a.side_tiles + a.top_tiles) {
+    const int j = (int)(tile - a.side_tiles);
+    strip = 1 + j % inner;
+    y0 = (j / inner) * a.border_rows;
+    y1 = y0 + a.border_rows < a.top_end ? y0 + a.border_rows : a.top_end;
+  } else if (tile < a.border_tiles) {
+    const int j = (int)(tile - a.side_tiles - a.top_tiles);
+    strip = 1 + j % inner;
+    y0 = a.bot_start + (j / inner) * a.border_rows;
+    y1 = y0 + a.border_rows;
+  } else {
+    const int64_t j = tile - a.border_tiles;
+    strip = 1 + (int)(j % inner);
+    y0 = a.top_end + (int)(j / inner) * a.seg_rows;
+    y1 = y0 + a.seg_rows < a.bot_start ? y0 + a.seg_rows : a.bot_start;
+  }
   const T* __restrict__ src = (const T*)a.src;
   T* __restrict__ dst = (T*)a.dst;
   const int r = a.r, r2 = 2 * a.r, ncols = 64 + 2 * a.r;
@@ -497,8 +523,7 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
   L.base = (uint32_t*)(lds + (size_t)wv * a.wave_bytes + window_base_offset(ncols));
   const int wave_dwords = a.wave_bytes / 4;
 
-  const int y0 = seg * a.seg_rows;
-  const int y1 = y0 + a.seg_rows < h ? y0 + a.seg_rows : h;
+  y1 = y1 < h ? y1 : h;
   const bool live = x0 + lane < w;
   constexpr int maxv = sizeof(T) == 2 ? 65535 : 255;
   const int rank = (int)a.rank;
@@ -540,6 +565,7 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
 
   place(estimate(32, y0));
   build(y0);
+  int prev = -1;  // this lane's result in the previous row
 
   for (int y = y0; y < y1; ++y) {
     // raw values of the next row step, loaded before they are needed
@@ -560,7 +586,7 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
     // uniform: by one subtree) or is rebuilt around the exact median of the
     // first pixel still open; results already found stay
     int res = 0;
-    bool have = false, done = true;
+    bool have = false, done = true, moved = false;
     for (int tries = 0;; ++tries) {
       RowOut o;
       if (ADAPT && !wide)
@@ -611,7 +637,12 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
           continue;
         }
       }
-      place(estimate((int)__builtin_ctzll(open), y));
+      // around the first open pixel's previous-row result (medians move
+      // little from row to row), else its exact median
+      const int fl = (int)__builtin_ctzll(open);
+      const int pm = readlane(prev, fl);
+      place(pm >= 0 && !moved ? pm : estimate(fl, y));
+      moved = pm >= 0;
       build(y);
     }
     if (!done) {
@@ -621,11 +652,13 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
       const int ny = (y / a.fb_rows + 1) * a.fb_rows;
       if (ny >= y1) return;
       y = ny - 1;
+      prev = -1;
       place(estimate(32, ny));
       build(ny);
       continue;
     }
     if (live) dst[(int64_t)y * a.drs + x0 + lane] = (T)res;
+    prev = live ? res : -1;
     if (y + 1 >= y1) break;
     const int off = res - (bc + 4 * q0);  // relative to the current scanned leaves
 
@@ -720,7 +753,11 @@ hipError_t launch_k(const WindowArgs& a, hipStream_t stream) {
   const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG>;
   hipError_t e = ensure_dynamic_lds(kern, lds);
   if (e != hipSuccess) return e;
-  const int64_t grid = ((int64_t)a.strips * a.segs + WPG - 1) / WPG;
+  const int inner = a.strips > 2 ? a.strips - 2 : 0;
+  const int64_t tiles =
+      (int64_t)a.border_tiles +
+      (inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0);
+  const int64_t grid = (tiles + WPG - 1) / WPG;
   hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG>), dim3((uint32_t)grid), dim3(64 * WPG),
                      lds, stream, a);
   return hipGetLastError();
