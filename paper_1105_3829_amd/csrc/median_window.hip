@@ -233,7 +233,7 @@ __device__ __forceinline__ int window_rank_exact(const T* __restrict__ src, int6
                                  int64_t xc, int64_t yc, int r, int rank, uint32_t* hist,
                                  int lane) {
   constexpr int kPasses = sizeof(T) == 2 ? 2 : 1;
-  constexpr int kB = 16;  // window rows loaded before any is counted
+  constexpr int kB = 32;  // window rows loaded before any is counted
   int k = rank, prefix = 0;
   for (int pass = 0; pass < kPasses; ++pass) {
     *(uint4*)(hist + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
@@ -302,6 +302,9 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
   for (int i = lane; i < wave_dwords / 4; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
   __builtin_amdgcn_wave_barrier();
   constexpr int kBatch = 16;
+  uint32_t lohi[KC];  // each lane alone updates its columns' lo/hi: kept in registers
+#pragma unroll
+  for (int k = 0; k < KC; ++k) lohi[k] = 0u;
   for (int j0 = -r; j0 <= r; j0 += kBatch) {
     const T* rows[kBatch];
 #pragma unroll
@@ -321,18 +324,23 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
           if (j0 + t <= r) {
             const Cls cl = classify(v[t], bc, q0, sq);
             lds_add(L.bins + c * kPitch + cl.q, cl.inc);
-            lds_add(L.lohi + c, cl.lh);
+            lohi[k] += cl.lh;
           }
         }
       }
     }
   }
+#pragma unroll
+  for (int k = 0; k < KC; ++k)
+    if (lane + 64 * k < ncols) L.lohi[lane + 64 * k] = lohi[k];
   __builtin_amdgcn_wave_barrier();
   if (lane <= kBinQ) {
     uint32_t s = 0;
     if (lane < kBinQ) {
+#pragma unroll 8
       for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * kPitch + lane];
     } else {
+#pragma unroll 8
       for (int c = 0; c <= 2 * r; ++c) s += L.lohi[c];
     }
     L.base[lane] = s;  // lane kBinQ writes base[kLohi]
@@ -340,32 +348,36 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
   __builtin_amdgcn_wave_barrier();
 }
 
-// Move the scanned dwords from [q0, q0 + s0) to [q1, q1 + s1): every column's
-// lo/hi gains or loses the leaves crossing the edges (column leaf bytes are
-// exact: at most 2r + 1 <= 255 values), then the base's lo/hi is summed again
-// from the columns.  All 64 lanes active.
+// Move the scanned dwords from [q0, q0 + s0) to [q1, q1 + s1) (all multiples
+// of 4): every column's lo gains the leaves of [q0, q1) (loses [q1, q0)) and
+// its hi loses the leaves of [q0 + s0, q1 + s1) (gains [q1 + s1, q0 + s0));
+// column leaf bytes are exact (at most 2r + 1 <= 255 values), so their digit
+// sums are the counts.  Then the base's lo/hi is summed again from the
+// columns.  All 64 lanes active.
 template <int KC>
 __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, int q0, int s0,
                                          int q1, int s1, int lane) {
+  const int la = q0 < q1 ? q0 : q1, lb = q0 < q1 ? q1 : q0;
+  const int e0 = q0 + s0, e1 = q1 + s1;
+  const int ha = e0 < e1 ? e0 : e1, hb = e0 < e1 ? e1 : e0;
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int c = lane + 64 * k;
     if (c < ncols) {
       const uint32_t* col = L.bins + c * kPitch;
-      uint32_t d = 0;  // lo gain + (hi gain << 16), modulo 2^32
-#pragma unroll
-      for (int q = 0; q < kBinQ; q += 4) {
+      uint32_t lo = 0, hi = 0;
+      for (int q = la; q < lb; q += 4) {
         const uint4 u = *(const uint4*)(col + q);
-        const uint32_t e[4] = {dsum(u.x, 0u), dsum(u.y, 0u), dsum(u.z, 0u), dsum(u.w, 0u)};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int qq = q + i;
-          const int lo = (qq < q1 ? 1 : 0) - (qq < q0 ? 1 : 0);
-          const int hi = (qq >= q1 + s1 ? 1 : 0) - (qq >= q0 + s0 ? 1 : 0);
-          d += (uint32_t)(lo + (hi << 16)) * e[i];
-        }
+        lo = dsum(u.w, dsum(u.z, dsum(u.y, dsum(u.x, lo))));
       }
-      lds_add(L.lohi + c, d);
+      for (int q = ha; q < hb; q += 4) {
+        const uint4 u = *(const uint4*)(col + q);
+        hi = dsum(u.w, dsum(u.z, dsum(u.y, dsum(u.x, hi))));
+      }
+      const uint32_t dlo = q1 > q0 ? lo : 0u - lo;
+      const uint32_t dhi = e1 > e0 ? 0u - hi : hi;
+      const uint32_t d = dlo + (dhi << 16);
+      if (d) lds_add(L.lohi + c, d);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -475,7 +487,9 @@ template <typename T, bool ADAPT, int KC, int WPG>
 __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  // the wave's index in the workgroup, as a value the compiler knows to be
+  // uniform: everything derived from it (tile, rows, range) stays scalar
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // tiles in launch order: short segments near the image's edges first (see
   // WindowArgs), then the inner strips' segments, neighbouring strips together
   const int64_t tile = (int64_t)blockIdx.x * WPG + wv;
@@ -767,7 +781,12 @@ template <typename T, bool ADAPT>
 hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
   const int kc = kc_for(a.r);
   const int wpg = window_waves_per_group(a.r);
-  if (kc <= 2) return launch_k<T, ADAPT, 2, 4>(a, stream);  // r <= 32
+  // r <= 32: one-wave workgroups let 11 waves share a CU (16-bit X-ray-like
+  // 4096^2 r = 15: 0.47 -> 0.41 ms); four-wave workgroups suit the 8-bit
+  // launches, which have four times the waves (8-bit low-key 8192^2 r = 8:
+  // 0.94 -> 0.87 ms)
+  if (kc <= 2)
+    return sizeof(T) == 2 ? launch_k<T, ADAPT, 2, 1>(a, stream) : launch_k<T, ADAPT, 2, 4>(a, stream);
   if (kc == 3) return wpg >= 4 ? launch_k<T, ADAPT, 3, 4>(a, stream)
                                : launch_k<T, ADAPT, 3, 2>(a, stream);
   return wpg >= 2 ? launch_k<T, ADAPT, 5, 2>(a, stream) : launch_k<T, ADAPT, 5, 1>(a, stream);
@@ -776,6 +795,7 @@ hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
 template <typename T, bool ADAPT>
 hipError_t prime_w() {
   const void* ks[] = {(const void*)k_median_window<T, ADAPT, 2, 4>,
+                      (const void*)k_median_window<T, ADAPT, 2, 1>,
                       (const void*)k_median_window<T, ADAPT, 3, 4>,
                       (const void*)k_median_window<T, ADAPT, 3, 2>,
                       (const void*)k_median_window<T, ADAPT, 5, 2>,
