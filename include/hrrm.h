@@ -149,6 +149,31 @@ int hrrm_rank2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, 
                 int64_t height, int64_t src_row_stride, int64_t dst_row_stride, int32_t r,
                 int64_t rank, int32_t drop_levels, hrrm_variant variant, void* hip_stream);
 
+/* ---- Allocation-free form ------------------------------------------------- */
+
+/* Largest number of tile flags hrrm_rank2d_noalloc keeps: one per 256-column x
+ * 16-row tile of the image, ceil(width / 256) * ceil(height / 16). */
+#define HRRM_NOALLOC_MAX_TILES 65536
+
+/* hrrm_rank2d (drop_levels = 0, PLAIN or ADAPTIVE) for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no hipMalloc, hipFree or other
+ * allocating routine.  The grey-level-window kernel's tile flags (the only
+ * device memory the 2-D path uses beyond the caller's buffers and LDS) live in
+ * a fixed array of HRRM_NOALLOC_MAX_TILES flags per GPU, held from the
+ * context's creation until the process ends, and are cleared by a small
+ * kernel at the start of every call that uses them.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (different
+ * streams or host threads, any context) race and must be ordered by the
+ * caller.  ADAPTIVE always takes the window kernel here (the adaptive tiered
+ * kernel needs a topology workspace).  Output equals hrrm_rank2d's.
+ * Errors as hrrm_rank2d, plus EUNSUPPORTED for an image with more than
+ * HRRM_NOALLOC_MAX_TILES tiles or for FULL_UPDATE. */
+int hrrm_rank2d_noalloc(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype,
+                        int64_t width, int64_t height, int64_t src_row_stride,
+                        int64_t dst_row_stride, int32_t r, int64_t rank, hrrm_variant variant,
+                        void* hip_stream);
+
 /* ---- Batched launch (many uneven images in one persistent kernel) --------- */
 
 /* One image of a batch.  Pointers are device pointers; strides in elements. */

@@ -86,6 +86,8 @@ def lib():
                 "hrrm_median3d": ([vp, vp, vp, i32, i64, i64, i64, i64, i64, i64, i64, i32, i32, vp],
                                   i32),
                 "hrrm_rank2d": ([vp, vp, vp, i32, i64, i64, i64, i64, i32, i64, i32, i32, vp], i32),
+                "hrrm_rank2d_noalloc": ([vp, vp, vp, i32, i64, i64, i64, i64, i32, i64, i32, vp],
+                                        i32),
                 "hrrm_median2d_video": ([vp, vp, vp, vp, i32, i64, i64, i64, i64, i64, i32, vp],
                                         i32),
                 "hrrm_median2d_batched": ([vp, ctypes.POINTER(_Image), i32, vp], i32),
@@ -209,6 +211,22 @@ class Context:
         check(lib().hrrm_rank2d(self._h, src.data_ptr(), out.data_ptr(), _dtype_code(src), w, h,
                                 src.stride(0), out.stride(0), r, k, drop_levels,
                                 _variant_code(variant), _stream_ptr(src, stream)))
+        return out
+
+    def rank2d_noalloc(self, src, r: int, rank: Optional[int] = None, variant="plain", out=None,
+                       stream=None):
+        """hrrm_rank2d_noalloc: as rank2d (full precision), with no device allocation."""
+        if src.dim() != 2 or src.stride(1) != 1:
+            raise ValueError("rank2d_noalloc takes a (H, W) tensor with contiguous rows")
+        out = self._out(src, out)
+        if out.stride(1) != 1:
+            raise ValueError("out rows must be contiguous")
+        h, w = src.shape
+        n = (2 * r + 1) ** 2
+        k = (n - 1) // 2 if rank is None else int(rank)
+        check(lib().hrrm_rank2d_noalloc(self._h, src.data_ptr(), out.data_ptr(), _dtype_code(src),
+                                        w, h, src.stride(0), out.stride(0), r, k,
+                                        _variant_code(variant), _stream_ptr(src, stream)))
         return out
 
     def median2d_video(self, src, r: int, estimate=None, out=None, stream=None):
@@ -436,7 +454,7 @@ def median2d_batched(srcs, radii, outs=None, stream=None):
 
 EXPORTED_SYMBOLS: List[str] = [
     "hrrm_last_error", "hrrm_version", "hrrm_ctx_create", "hrrm_ctx_destroy", "hrrm_ctx_reserve",
-    "hrrm_median2d", "hrrm_median3d", "hrrm_rank2d", "hrrm_median2d_video",
+    "hrrm_median2d", "hrrm_median3d", "hrrm_rank2d", "hrrm_rank2d_noalloc", "hrrm_median2d_video",
     "hrrm_median2d_batched",
     "hrrm_batch_capacity", "hrrm_autotune", "hrrm_load_tuning", "hrrm_save_tuning",
     "hrrm_set_tile_config",

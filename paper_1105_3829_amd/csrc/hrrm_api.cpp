@@ -21,7 +21,16 @@ namespace hrrm {
 
 namespace {
 thread_local std::string g_err;
-}
+
+// Tile flags of hrrm_rank2d_noalloc: a fixed device array (one copy per GPU,
+// held until the process ends).  Host code never uses the array's name as an
+// address: its device address on each GPU comes from hipGetSymbolAddress,
+// taken once per device when a context is created there.
+static __device__ __align__(256) uint32_t scratch[HRRM_NOALLOC_MAX_TILES];
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 256;
+uint32_t* g_scratch_ptr[kMaxDevices];
+}  // namespace
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -38,6 +47,21 @@ int fail_hip(hipError_t e, const char* what) {
 }
 
 void clear_error() { g_err.clear(); }
+
+// Device address of `scratch` on the current device `dev` (looked up once).
+int scratch_address(int dev, uint32_t** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(HRRM_EUNSUPPORTED, "device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = (uint32_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HRRM_OK;
+}
+
 
 const char* last_error() { return g_err.c_str(); }
 
@@ -343,6 +367,13 @@ static int run_window(Context* ctx, const TileConfig& t, const void* src, void* 
   if (!need_buf) {
     rc = ctx->ensure_need(tiles, stream, &need_buf);
     if (rc != HRRM_OK) return rc;
+  } else {
+    // a fixed flag array: its flags start clear only by clearing them here
+    if (tiles > HRRM_NOALLOC_MAX_TILES)
+      return fail(HRRM_EUNSUPPORTED, "%lld tiles, more than the %d flags of the fixed array",
+                  (long long)tiles, HRRM_NOALLOC_MAX_TILES);
+    e = launch_clear_flags(need_buf, tiles, stream);
+    if (e != hipSuccess) return fail_hip(e, "tile flag clear");
   }
   wa.need = need_buf;
   fa.need = need_buf;
@@ -381,6 +412,32 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
     if (e != hipSuccess) return fail_hip(e, "adaptive topology launch");
   }
   e = launch_median(a, bytes, dims, adaptive, tiered, full, stream);
+  if (e != hipSuccess) return fail_hip(e, "median kernel launch");
+  return HRRM_OK;
+}
+
+// hrrm_rank2d_noalloc: the window kernel with the fixed flag array, or the
+// tiered kernel (uniform tree), which uses no device memory of its own.
+int run_noalloc(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
+                int64_t srs, int64_t drs, int r, int64_t rank, int variant, hipStream_t stream) {
+  const int bytes = dtype == HRRM_U8 ? 1 : 2;
+  const bool adaptive = variant == HRRM_ADAPTIVE;
+  TileConfig t = ctx->tile_for(bytes, 2, r, adaptive, w, h, 1);
+  if (adaptive && t.window_rows <= 0) t.window_rows = 32;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+  if (t.window_rows > 0) {
+    uint32_t* flags = nullptr;
+    const int rc = scratch_address(ctx->device, &flags);
+    if (rc != HRRM_OK) return rc;
+    return run_window(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, adaptive, stream, flags);
+  }
+  MedianArgs a;
+  bool tiered = true;
+  int rc = tiered_args(t, bytes, 2, false, false, src, dst, w, h, 1, srs, 0, drs, 0, r, rank, 0,
+                       a, tiered);
+  if (rc != HRRM_OK) return rc;
+  e = launch_median(a, bytes, 2, false, tiered, false, stream);
   if (e != hipSuccess) return fail_hip(e, "median kernel launch");
   return HRRM_OK;
 }
@@ -490,6 +547,23 @@ int hrrm_ctx_create(int device, hrrm_ctx* out) {
   Context* c = new (std::nothrow) Context();
   if (!c) return fail(HRRM_ENOMEM, "out of host memory");
   c->device = device;
+  {
+    // the fixed flag array's address on this device, once per device
+    int prev = 0;
+    e = hipGetDevice(&prev);
+    if (e == hipSuccess) e = hipSetDevice(device);
+    if (e != hipSuccess) {
+      delete c;
+      return fail_hip(e, "hipSetDevice");
+    }
+    uint32_t* p = nullptr;
+    const int rc = scratch_address(device, &p);
+    (void)hipSetDevice(prev);
+    if (rc != HRRM_OK) {
+      delete c;
+      return rc;
+    }
+  }
   if (const char* tc = getenv("HRRM_TUNE_CACHE")) {
     if (FILE* f = fopen(tc, "r")) {
       fclose(f);
@@ -563,6 +637,27 @@ int hrrm_rank2d(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype, 
   if (width == 0 || height == 0) return HRRM_OK;
   return run_filter(c, d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride,
                     0, r, rank, drop_levels, variant, 2, (hipStream_t)hip_stream, nullptr);
+}
+
+int hrrm_rank2d_noalloc(hrrm_ctx ctx, const void* d_src, void* d_dst, hrrm_dtype dtype,
+                        int64_t width, int64_t height, int64_t src_row_stride,
+                        int64_t dst_row_stride, int32_t r, int64_t rank, hrrm_variant variant,
+                        void* hip_stream) {
+  clear_error();
+  Context* c = reinterpret_cast<Context*>(ctx);
+  if (!c) return fail(HRRM_EINVAL, "null context");
+  int rc = check_variant(variant, dtype);
+  if (rc != HRRM_OK) return rc;
+  if (variant == HRRM_FULL_UPDATE)
+    return fail(HRRM_EUNSUPPORTED, "the allocation-free form takes PLAIN or ADAPTIVE");
+  rc = validate(d_src, d_dst, dtype, width, height, 1, src_row_stride, 0, dst_row_stride, 0, r, 2);
+  if (rc != HRRM_OK) return rc;
+  const int64_t n = (int64_t)(2 * r + 1) * (2 * r + 1);
+  if (rank < 0 || rank >= n) return fail(HRRM_EINVAL, "rank %lld outside 0..%lld", (long long)rank,
+                                         (long long)(n - 1));
+  if (width == 0 || height == 0) return HRRM_OK;
+  return run_noalloc(c, d_src, d_dst, dtype, width, height, src_row_stride, dst_row_stride, r,
+                     rank, variant, (hipStream_t)hip_stream);
 }
 
 int hrrm_median2d_video(hrrm_ctx ctx, const void* d_src, void* d_dst, const void* d_estimate,

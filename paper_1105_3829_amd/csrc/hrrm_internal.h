@@ -130,6 +130,8 @@ int window_waves_per_group(int r);
 // tree's pairs of 64-leaf subtrees (128 leaves)
 hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStream_t stream);
 hipError_t prime_window_lds();
+// Zero n tile flags on `stream` with a fill kernel (no memset node in graphs).
+hipError_t launch_clear_flags(uint32_t* p, int64_t n, hipStream_t stream);
 
 // Launch the fused median kernel.  dims = 2 or 3; full = update every node of
 // the window tree at every pixel (8-bit dense storage only).  Returns

@@ -826,6 +826,19 @@ hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStrea
   return adaptive ? launch_w<uint16_t, true>(a, stream) : launch_w<uint16_t, false>(a, stream);
 }
 
+__global__ void k_clear_flags(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_clear_flags(uint32_t* p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256 < 64 ? (n + 255) / 256 : 64;
+  hipLaunchKernelGGL(k_clear_flags, dim3((uint32_t)blocks), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
 hipError_t prime_window_lds() {
   hipError_t e = prime_w<uint8_t, true>();
   if (e == hipSuccess) e = prime_w<uint8_t, false>();
