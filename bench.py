@@ -3,14 +3,25 @@
 
 Default workload: 16-bit 4096 x 4096 X-ray-like image (12-bit Gaussian mixture
 plus a smooth ramp), radius 15 (31 x 31 window), clamp-to-edge, plain
-(uniform-tree) variant.  One step = one full filter pass over one image that is
-already resident in HBM; the timed region rotates over input/output copies
-larger than the 256 MB last-level cache so every step reads from HBM.
+(uniform-tree) variant, default tile configuration.  One step = one full
+filter pass over one image that is already resident in HBM; the timed region
+rotates over input/output copies larger than the 256 MB last-level cache so
+every step reads from HBM.
 
 Prints ONE JSON line.  Besides the throughput it carries
-  * roofline: the LDS bound of the kernel (algorithmic LDS work per pixel from
-    the input histogram) against the LDS peak, the kernel time
-    taken from HIP events on the launch stream, with the HBM view alongside;
+  * roofline: the LDS bound of the filter (algorithmic LDS work per pixel from
+    the input histogram) against the LDS read bandwidth measured in this run
+    by a peak kernel (the nominal 256 CUs x 128 B x 2.4 GHz beside it), the
+    step's kernel time taken from HIP events on the launch stream, and the HBM
+    view against the published 8 TB/s, with a streaming copy measured in this
+    run beside it;
+  * variants: the adaptive tree on the same image;
+  * sweeps: radius sweeps of the other workloads (8-bit 8192^2 low-key image,
+    r = 1..100; 16-bit 512 x 512 x 256 volume, r = 1..7; the 16-bit image at
+    r = 5 and 50), one pass each after a warm-up;
+  * serving: the Poisson request trace at 2000 req/s, and a ladder of
+    offered rates giving each mode's highest rate served within the latency
+    bound;
   * cpu_baseline: the brute-force CPU oracle timed on a band of full rows of
     the same image on this host's cores.
 
@@ -21,6 +32,8 @@ Prints ONE JSON line.  Besides the throughput it carries
 from __future__ import annotations
 
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -30,9 +43,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "output Mpix/s (u16 4096², r=15) + % HBM/LDS roofline; serving p50/p99 ms"
-HBM_PEAK_GBS = 8000.0
-# LDS: 256 CUs x 32 banks x 4 B per clock x 2.4 GHz
-LDS_PEAK_GBS = 256 * 32 * 4 * 2.4
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+# LDS, nominal: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_NOMINAL_GBS = 256 * 128 * 2.4
+SERVING_SLO_MS = 20.0  # p99 latency bound of the serving ladder
 
 
 def workload(name: str, r: int):
@@ -67,10 +81,29 @@ def lds_work_per_pixel(img, variant: str = "plain", r: int = 0) -> tuple:
     return 2.0 * zbar * per_step + 2.0 * nodes, zbar, d
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(img, r: int, seconds_target: float = 10.0):
     import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    threads = host_threads()
+    model = cpu_model()
     if img.ndim == 3:
         # a slab of whole slices, clamped at the slab's own bottom slice
         d, h, w = img.shape
@@ -84,7 +117,7 @@ def cpu_baseline(img, r: int, seconds_target: float = 10.0):
         oracle.median3d(slab, r, threads=threads)
         dt = time.perf_counter() - t
         return {"value": round(slab.size / dt / 1e6, 4), "unit": "Mvox/s", "cores": threads,
-                "kind": "oracle",
+                "kind": "oracle", "cpu": model,
                 "sample": "slices 0..%d of the same volume (%d x %d x %d voxels, clamp at the "
                           "slab's own last slice), brute-force nth_element per window, %.1f s" % (
                               n - 1, w, h, n, dt)}
@@ -100,10 +133,32 @@ def cpu_baseline(img, r: int, seconds_target: float = 10.0):
     oracle.median2d(band, r, threads=threads)
     dt = time.perf_counter() - t
     return {"value": round(band.size / dt / 1e6, 4), "unit": "Mpix/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu": model,
             "sample": "rows 0..%d of the same image (%d x %d pixels, clamp at the image's own "
                       "top border), brute-force nth_element per window, %.1f s" % (rows - 1, w, rows,
                                                                                   dt)}
+
+
+def measure_peaks():
+    """LDS read and HBM streaming-copy bandwidth measured now, on this GPU."""
+    from paper_1105_3829_amd import build as b
+    if not os.path.exists(b.MEASURE_LIB):
+        return None
+    L = ctypes.CDLL(b.MEASURE_LIB)
+    L.hrrm_measure_lds_read.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.hrrm_measure_hbm_copy.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double)]
+    lds = ctypes.c_double(0)
+    hbm = ctypes.c_double(0)
+    nbytes = 1 << 30  # 1 GiB each way: far above the 256 MB last-level cache
+    if L.hrrm_measure_lds_read(0, 5, ctypes.byref(lds)) != 0:
+        return None
+    if L.hrrm_measure_hbm_copy(0, nbytes, 5, ctypes.byref(hbm)) != 0:
+        return None
+    return {"lds_read_gbs": round(lds.value / 1e9, 1), "hbm_copy_gbs": round(hbm.value / 1e9, 1),
+            "hbm_copy_bytes": nbytes,
+            "how": "best of 5: conflict-free ds_read_b128 from two 64 KB workgroups per CU; "
+                   "a streaming uint4 copy of 1 GiB between two buffers (read + write bytes)"}
 
 
 def serving(seconds: float, warmup_s: float = 0.5, rate: float = 2000.0, per_image: bool = False,
@@ -128,8 +183,8 @@ def serving(seconds: float, warmup_s: float = 0.5, rate: float = 2000.0, per_ima
     while ndone < n:
         now = srv.now()
         if time.time() - last_note > 5.0:
-            print("serving %s: t=%.1fs submitted %d/%d done %d" % (
-                "per-image" if per_image else "batched", now - t0, i, n, ndone),
+            print("serving %s %.0f/s: t=%.1fs submitted %d/%d done %d" % (
+                "per-image" if per_image else "batched", rate, now - t0, i, n, ndone),
                 file=sys.stderr, flush=True)
             last_note = time.time()
         while i < n and t0 + trace[i].arrival_s <= now:
@@ -165,6 +220,7 @@ def serving(seconds: float, warmup_s: float = 0.5, rate: float = 2000.0, per_ima
     pix_all = sum(p for _, p in done_pairs)
     return {
         "mode": "per_image" if per_image else "batched",
+        "rate_hz": rate,
         "requests": len(measured),
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -184,6 +240,138 @@ def serving_pools():
     return {"u16": u16, "u8": u8}
 
 
+def serving_ladder(pools, rates, seconds):
+    """Each mode at increasing offered rates: the highest rate whose queue is
+    stable with p99 latency within SERVING_SLO_MS is the mode's capacity."""
+    out = {"slo_p99_ms": SERVING_SLO_MS, "seconds_per_rate": seconds, "rates": list(rates)}
+    for per_image in (False, True):
+        mode = "per_image" if per_image else "batched"
+        runs = []
+        best = None
+        for rate in rates:
+            r = serving(seconds, rate=rate, per_image=per_image, pools=pools)
+            runs.append(r)
+            if r["queue_stable"] and r["p99_ms"] <= SERVING_SLO_MS:
+                best = r
+            elif best is not None:
+                break  # past capacity
+        out[mode] = {"runs": runs,
+                     "max_rate_hz_within_slo": best["rate_hz"] if best else None,
+                     "mpix_s_within_slo": best["completed_mpix_s_in_window"] if best else None}
+    b, p = out["batched"]["mpix_s_within_slo"], out["per_image"]["mpix_s_within_slo"]
+    out["throughput_gain_at_slo"] = round(b / p, 3) if b and p else None
+    return out
+
+
+def timed_steps(ctx, srcs, outs, r, variant, steps, warmup, stream, vol):
+    """ms per step (wall clock) and the mean step time from HIP events on the
+    launch stream, rotating over the given input/output copies."""
+    import numpy as np
+    import torch
+    copies = len(srcs)
+
+    def step(i):
+        if vol:
+            ctx.median3d(srcs[i % copies], r, variant=variant, out=outs[i % copies], stream=stream)
+        else:
+            ctx.median2d(srcs[i % copies], r, variant=variant, out=outs[i % copies], stream=stream)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        step(i)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def roofline(img, variant, r, kernel_ms, pixels, peaks):
+    a_ops, zbar, d = lds_work_per_pixel(img, variant, r)
+    lds_bytes = a_ops * 4.0 * pixels
+    hbm_bytes = 2.0 * img.dtype.itemsize * pixels
+    lds_gbs = lds_bytes / (kernel_ms * 1e-3) / 1e9
+    hbm_gbs = hbm_bytes / (kernel_ms * 1e-3) / 1e9
+    lds_peak = peaks["lds_read_gbs"] if peaks else LDS_NOMINAL_GBS
+    return {"bound": "lds", "achieved": round(lds_gbs, 2), "peak": lds_peak, "unit": "GB/s",
+            "frac": round(lds_gbs / lds_peak, 5),
+            "peak_source": "measured in this run (LDS read kernel)" if peaks else "nominal",
+            "peak_nominal": LDS_NOMINAL_GBS, "frac_nominal": round(lds_gbs / LDS_NOMINAL_GBS, 5),
+            "kernel_ms": round(kernel_ms, 4), "lds_dword_ops_per_pixel": round(a_ops, 3),
+            "zbar": round(zbar, 4),
+            "hbm": {"achieved": round(hbm_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 6), "bytes_per_launch": hbm_bytes,
+                    "copy_measured_gbs": peaks["hbm_copy_gbs"] if peaks else None}}
+
+
+def stored_traffic(workload, r, variant):
+    """HBM traffic per launch from rocprofv3 counters (FETCH_SIZE, WRITE_SIZE,
+    scaled by the same counters of a plain copy), taken for the kernel source
+    as it was; null once that source has changed."""
+    tfile = os.path.join(ROOT, "profiles", "hbm_traffic_%s_r%d_%s.json" % (workload, r, variant))
+    if not os.path.exists(tfile):
+        return None, None
+    try:
+        t = json.load(open(tfile))
+    except Exception:
+        return None, None
+    name = t.get("kernel_source")
+    src = os.path.join(ROOT, "paper_1105_3829_amd", "csrc", name) if name else ""
+    if not name or not os.path.isfile(src):
+        return None, "no counters for the current kernel"
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if digest != t.get("kernel_source_sha256"):
+        return None, "stale: %s changed since the counters were taken" % t.get("kernel_source")
+    return t.get("bytes_per_launch"), t.get("source")
+
+
+def sweeps(ctx, stream, steps=5, warmup=2):
+    """Radius sweeps: one image on the device, `steps` timed passes per radius."""
+    import numpy as np
+    import torch
+    from paper_1105_3829_amd import datagen
+    out = {}
+
+    def dev(a):
+        t = torch.from_numpy(a)
+        if t.dtype == torch.uint16:
+            return t.view(torch.int16).to("cuda:0").view(torch.uint16)
+        return t.to("cuda:0")
+
+    def run(key, img, radii, variants, vol=False):
+        d = dev(img)
+        o = torch.empty_like(d)
+        res = {}
+        for variant in variants:
+            row = {}
+            for r in radii:
+                _, k_ms = timed_steps(ctx, [d], [o], r, variant, steps, warmup, stream, vol)
+                row[str(r)] = {"kernel_ms": round(k_ms, 4), "mpix_s": round(img.size / k_ms / 1e3, 1)}
+            rates = [v["mpix_s"] for v in row.values()]
+            row["min_over_max"] = round(min(rates) / max(rates), 3)
+            res[variant] = row
+        out[key] = res
+        del d, o
+        torch.cuda.synchronize()
+
+    print("sweeps: 8-bit 8192^2 low-key", file=sys.stderr, flush=True)
+    run("c2_u8_8192x8192_lowkey", datagen.lowkey_u8(8192, 8192, seed=2),
+        (1, 2, 4, 8, 16, 32, 64, 100), ("plain", "adaptive"))
+    print("sweeps: 16-bit 512x512x256 volume", file=sys.stderr, flush=True)
+    run("c3_u16_512x512x256_volume", datagen.xray_volume_u16(256, 512, 512, seed=3),
+        (1, 2, 3, 5, 7), ("plain", "adaptive"), vol=True)
+    print("sweeps: 16-bit 4096^2 x-ray", file=sys.stderr, flush=True)
+    run("c1_u16_4096x4096_xray", datagen.xray_u16(4096, 4096, seed=1), (5, 15, 50),
+        ("plain", "adaptive"))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,13 +382,14 @@ def main():
     ap.add_argument("--variant", default="plain")
     ap.add_argument("--copies", type=int, default=0, help="input/output copies rotated over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweeps", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of one image (counter calibration)")
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the replayed serving trace (0 = skip serving)")
-    ap.add_argument("--saturation-rate", type=float, default=4000.0,
-                    help="request rate of the overload trace (0 = skip it)")
-    ap.add_argument("--saturation-seconds", type=float, default=2.5)
+    ap.add_argument("--ladder-rates", default="2000,3000,4000,5000,6000",
+                    help="offered rates of the serving ladder (empty = skip it)")
+    ap.add_argument("--ladder-seconds", type=float, default=2.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -214,6 +403,7 @@ def main():
 
     import paper_1105_3829_amd as hrrm
 
+    peaks = measure_peaks()
     img, desc = workload(args.workload, args.r)
     vol = img.ndim == 3
     depth = img.shape[0] if vol else 1
@@ -230,51 +420,22 @@ def main():
     outs = [torch.empty_like(base) for _ in range(copies)]
     ctx = hrrm.context(0)
     stream = torch.cuda.current_stream(dev)
-
-    def step(i):
-        if vol:
-            ctx.median3d(srcs[i % copies], args.r, variant=args.variant, out=outs[i % copies],
-                         stream=stream)
-        else:
-            ctx.median2d(srcs[i % copies], args.r, variant=args.variant, out=outs[i % copies],
-                         stream=stream)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
     if args.copy_calibration:
         tmp = torch.empty_like(base)
         tmp.copy_(srcs[0])
         torch.cuda.synchronize()
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        evs[i][0].record(stream)
-        step(i)
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_per_step, kernel_ms = timed_steps(ctx, srcs, outs, args.r, args.variant, args.steps,
+                                         args.warmup, stream, vol)
     pixels = h * w * depth
     value = pixels / (ms_per_step * 1e-3) / 1e6
-
-    a_ops, zbar, d = lds_work_per_pixel(img, args.variant, args.r)
-    lds_bytes_launch = a_ops * 4.0 * pixels
-    hbm_bytes_launch = 2.0 * img.dtype.itemsize * pixels
-    lds_gbs = lds_bytes_launch / (kernel_ms * 1e-3) / 1e9
-    hbm_gbs = hbm_bytes_launch / (kernel_ms * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "hbm_traffic_%s_r%d_%s.json" % (args.workload, args.r,
-                                                                           args.variant))
-    if os.path.exists(tfile):
-        try:
-            traffic = json.load(open(tfile)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    roof = roofline(img, args.variant, args.r, kernel_ms, pixels, peaks)
+    roof["traffic"], roof["traffic_source"] = stored_traffic(args.workload, args.r, args.variant)
+    roof["kernel_ms_covers"] = ("every launch of a step: for the 2-D window kernel, that kernel "
+                                "plus the tiered kernel's pass over the tiles it flags")
+    other = "adaptive" if args.variant == "plain" else "plain"
+    o_ms, o_kms = timed_steps(ctx, srcs, outs, args.r, other, args.steps, args.warmup, stream,
+                              vol)
 
     res = {
         "metric": METRIC,
@@ -293,14 +454,16 @@ def main():
             desc, args.r, "x".join([str(2 * args.r + 1)] * (3 if vol else 2)), args.variant),
             "width": w, "height": h, **({"depth": depth} if vol else {}), "r": args.r,
             "variant": args.variant, "input_copies": copies},
-        "roofline": {"bound": "lds", "achieved": round(lds_gbs, 2), "peak": LDS_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(lds_gbs / LDS_PEAK_GBS, 5),
-                     "traffic": traffic, "kernel_ms": round(kernel_ms, 4),
-                     "lds_dword_ops_per_pixel": round(a_ops, 3), "zbar": round(zbar, 4),
-                     "hbm": {"achieved": round(hbm_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": round(hbm_gbs / HBM_PEAK_GBS, 6),
-                             "bytes_per_launch": hbm_bytes_launch}},
+        "roofline": roof,
+        "peaks": peaks,
+        "variants": {other: {"value": round(pixels / (o_ms * 1e-3) / 1e6, 2),
+                             "ms_per_step": round(o_ms, 4),
+                             "roofline": roofline(img, other, args.r, o_kms, pixels, peaks)}},
     }
+    del srcs, outs
+    torch.cuda.synchronize()
+    if not args.no_sweeps and args.workload == "c1":
+        res["sweeps"] = sweeps(ctx, stream)
     if args.serving_seconds > 0:
         print("serving: drawing request pools", file=sys.stderr, flush=True)
         pools = serving_pools()
@@ -314,18 +477,9 @@ def main():
             "p50_ms": b["p50_ms"], "p99_ms": b["p99_ms"],
             "throughput_gain": round(b["completed_mpix_s_in_window"] /
                                      max(p["completed_mpix_s_in_window"], 1e-9), 3)}
-        if args.saturation_rate > 0:
-            # the same trace recipe at a rate neither mode can sustain: the
-            # completed throughput inside the window is each mode's capacity
-            sb = serving(args.saturation_seconds, rate=args.saturation_rate, per_image=False,
-                         pools=pools)
-            sp = serving(args.saturation_seconds, rate=args.saturation_rate, per_image=True,
-                         pools=pools)
-            res["serving"]["saturated"] = {
-                "rate_hz": args.saturation_rate, "seconds": args.saturation_seconds,
-                "batched": sb, "per_image": sp,
-                "throughput_gain": round(sb["completed_mpix_s_in_window"] /
-                                         max(sp["completed_mpix_s_in_window"], 1e-9), 3)}
+        rates = [float(x) for x in args.ladder_rates.split(",") if x.strip()]
+        if rates:
+            res["serving"]["ladder"] = serving_ladder(pools, rates, args.ladder_seconds)
     if not args.no_cpu_baseline:
         print("cpu baseline: timing the oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(img, args.r)

@@ -62,6 +62,23 @@ def _compile(src: str) -> str:
     return obj
 
 
+MEASURE_SRC = os.path.join(HERE, "measure", "peaks.hip")
+MEASURE_LIB = os.path.join(HERE, "libhrrm_measure.so")
+
+
+def build_measure(verbose: bool = True) -> str:
+    """libhrrm_measure.so: the benchmark's peak-bandwidth kernels (not the filter)."""
+    tmp = MEASURE_LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + DEVICE + COMMON + ["-shared", MEASURE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    os.replace(tmp, MEASURE_LIB)
+    if verbose:
+        print("built", MEASURE_LIB)
+    return MEASURE_LIB
+
+
 def build(verbose: bool = True) -> str:
     """Compile every source for gfx950 and link libhrrm.so.  Returns its path."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]

@@ -55,6 +55,15 @@ def test_u16_xray_radii(hrrm, r):
     _check2d(hrrm, img, r)
 
 
+@pytest.mark.parametrize("r", [64, 100, 127])
+def test_u16_xray_large_radii_default_tiles(hrrm, r):
+    # the 16-bit defaults past r = 63 (whole-LDS tiered tiles, or the window
+    # kernel), on an image a few strips wide
+    img = datagen.xray_u16(70, 300, seed=30 + r)
+    _check2d(hrrm, img, r)
+    _check2d(hrrm, img, r, variant="adaptive")
+
+
 @pytest.mark.parametrize("r", [1, 3, 4, 7, 15])
 def test_u16_full_range_many_subtrees(hrrm, r):
     # i.i.d. full-range values: medians scatter over many deep subtrees, which
