@@ -387,7 +387,7 @@ def main():
                     help="also run a plain device copy of one image (counter calibration)")
     ap.add_argument("--serving-seconds", type=float, default=5.0,
                     help="length of the replayed serving trace (0 = skip serving)")
-    ap.add_argument("--ladder-rates", default="2000,3000,4000,5000,6000",
+    ap.add_argument("--ladder-rates", default="2000,2500,3000,3500,4000,4500,5000",
                     help="offered rates of the serving ladder (empty = skip it)")
     ap.add_argument("--ladder-seconds", type=float, default=2.0)
     args = ap.parse_args()

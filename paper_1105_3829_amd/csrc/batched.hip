@@ -10,6 +10,12 @@
 // into a HIP graph and replayed; a batch only uploads its descriptors (into a
 // device buffer owned by that stream's entry) before the replay.  The counter
 // is reset by a kernel node, not a memset node.
+//
+// Images whose tile configuration picks the grey-level-window kernel (and
+// whose radius fits its two-column build, r <= 32) are not part of the
+// persistent launch: they run as one multi-image window launch per element
+// type, followed by one tiered pass per image over the tiles the window
+// kernel flagged, all before the graph on the same stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,7 +42,9 @@ constexpr int kBatchMaxR = 127;
 // two fixed regions (the captured launches keep their pointers).
 constexpr size_t kDescOffset = 256;
 constexpr size_t kClassBytes = sizeof(BatchImage) * kBatchCap;
-constexpr size_t kBatchBytes = kDescOffset + 2 * kClassBytes;
+// then the window launches' descriptors (both element types, kBatchCap in all)
+constexpr size_t kWinOffset = (kDescOffset + 2 * kClassBytes + 255) & ~(size_t)255;
+constexpr size_t kBatchBytes = kWinOffset + sizeof(WindowImage) * kBatchCap;
 
 BatchStream* Context::batch_for(hipStream_t s) {
   for (auto& b : batch)
@@ -83,6 +91,11 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
   // (no subtree counted wave-wide, only slot 0 in use); heavy class: the rest
   std::vector<BatchImage> descs, light;
   descs.reserve(count);
+  // window-kernel images by element type (u8, u16), with their fallback passes
+  std::vector<WindowImage> wins[2];
+  std::vector<MedianArgs> fbs[2];
+  int win_rmax[2] = {0, 0};
+  int64_t need_tiles = 0;
   int64_t tiles = 0;
   for (int i = 0; i < count; ++i) {
     const hrrm_image& im = images[i];
@@ -93,6 +106,22 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     if (im.width == 0 || im.height == 0) continue;
     const int bytes = im.dtype == HRRM_U8 ? 1 : 2;
     const TileConfig t = ctx->tile_for(bytes, 2, im.r, false, im.width, im.height, 1, false);
+    if (t.window_rows > 0 && window_multi_waves(bytes, im.r) > 0) {
+      WindowImage wi{};
+      MedianArgs fa;
+      const int64_t n = (int64_t)(2 * im.r + 1) * (2 * im.r + 1);
+      int rc = window_setup(ctx, t, im.src, im.dst, bytes, im.width, im.height, im.src_row_stride,
+                            im.dst_row_stride, im.r, (n - 1) / 2, wi.args, fa);
+      if (rc != HRRM_OK) return fail(rc, "image %d: %s", i, hrrm_last_error());
+      // the flag offset for now; the pointer once the flag buffer is known
+      wi.args.need = nullptr;
+      fa.need = (uint32_t*)(uintptr_t)need_tiles;
+      need_tiles += (int64_t)fa.strips * fa.segs;
+      wins[bytes - 1].push_back(wi);
+      fbs[bytes - 1].push_back(fa);
+      win_rmax[bytes - 1] = std::max(win_rmax[bytes - 1], im.r);
+      continue;
+    }
     BatchImage b{};
     MedianArgs& a = b.args;
     a.src = im.src;
@@ -120,7 +149,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
     a.min_group = std::max(1, t.min_group);
     a.max_groups = std::max(0, t.max_groups);
     a.raw_window = std::max(0, t.raw_window);
-    a.mfma = 2 * im.r + 1 <= 127;  // column counts as signed bytes
+    a.mfma = bytes == 1 && 2 * im.r + 1 <= 127;  // as for a single 2-D launch
     const size_t meta = tiered_meta_bytes(im.r, bytes) + 16;
     const size_t slot_bytes = (size_t)a.cp * 16;
     const int64_t span = 2 * im.r + 1;
@@ -142,7 +171,37 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
   }
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
-  if (descs.empty() && light.empty()) return HRRM_OK;
+  const bool any_win = !wins[0].empty() || !wins[1].empty();
+  if (descs.empty() && light.empty() && !any_win) return HRRM_OK;
+  uint32_t* need_buf = nullptr;
+  int64_t groups[2] = {0, 0};
+  if (any_win) {
+    int rc = ctx->ensure_need(need_tiles, stream, &need_buf);
+    if (rc != HRRM_OK) return rc;
+    for (int c = 0; c < 2; ++c) {
+      // larger images first: their many workgroups start early, small ones
+      // fill the tail
+      std::vector<size_t> order(wins[c].size());
+      for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+      std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        return wins[c][x].args.w * wins[c][x].args.h > wins[c][y].args.w * wins[c][y].args.h;
+      });
+      std::vector<WindowImage> sorted;
+      sorted.reserve(order.size());
+      const int wpg = window_multi_waves(c + 1, win_rmax[c]);
+      for (size_t k : order) {
+        WindowImage wi = wins[c][k];
+        MedianArgs& fa = fbs[c][k];
+        fa.need = need_buf + (uintptr_t)fa.need;
+        wi.args.need = fa.need;
+        groups[c] += (window_tiles(wi.args) + wpg - 1) / wpg;
+        wi.group_end = groups[c];
+        sorted.push_back(wi);
+      }
+      wins[c].swap(sorted);
+      if (groups[c] > 0x7fffffffLL) return fail(HRRM_EUNSUPPORTED, "batch has too many tiles");
+    }
+  }
   // per class, longest work first: expensive images (16-bit, larger windows)
   // at the front of every chunk's range shortens the tail of the launch
   for (auto* v : {&light, &descs}) {
@@ -178,15 +237,36 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
   std::memcpy(stage + 64, n, sizeof n);
   std::memcpy(stage + kDescOffset, light.data(), sizeof(BatchImage) * light.size());
   std::memcpy(stage + kDescOffset + kClassBytes, descs.data(), sizeof(BatchImage) * descs.size());
+  std::memcpy(stage + kWinOffset, wins[0].data(), sizeof(WindowImage) * wins[0].size());
+  std::memcpy(stage + kWinOffset + sizeof(WindowImage) * wins[0].size(), wins[1].data(),
+              sizeof(WindowImage) * wins[1].size());
   e = hipMemcpyAsync(base + 64, stage + 64, kDescOffset - 64 + sizeof(BatchImage) * light.size(),
                      hipMemcpyHostToDevice, stream);
   if (e == hipSuccess && !descs.empty())
     e = hipMemcpyAsync(base + kDescOffset + kClassBytes, stage + kDescOffset + kClassBytes,
                        sizeof(BatchImage) * descs.size(), hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess && any_win)
+    e = hipMemcpyAsync(base + kWinOffset, stage + kWinOffset,
+                       sizeof(WindowImage) * (wins[0].size() + wins[1].size()),
+                       hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return fail_hip(e, "batch descriptor upload");
   e = hipEventRecord(bs->staged, stream);
   if (e != hipSuccess) return fail_hip(e, "batch staging event");
   bs->pending = true;
+  if (any_win) {
+    const WindowImage* d_win = (const WindowImage*)(base + kWinOffset);
+    for (int c = 1; c >= 0; --c) {  // 16-bit images first: the longer work
+      const WindowImage* d = d_win + (c == 1 ? wins[0].size() : 0);
+      e = launch_window_multi(d, (int)wins[c].size(), groups[c], c + 1, win_rmax[c], stream);
+      if (e != hipSuccess) return fail_hip(e, "window kernel launch (batch)");
+    }
+    for (int c = 1; c >= 0; --c)
+      for (const MedianArgs& fa : fbs[c]) {
+        e = launch_median(fa, c + 1, 2, false, true, false, stream);
+        if (e != hipSuccess) return fail_hip(e, "median kernel launch (batch fallback)");
+      }
+    if (descs.empty() && light.empty()) return HRRM_OK;
+  }
   const size_t lds[2] = {kBatchLightLds, kBatchLds};
   const int grid[2] = {batched_grid(ctx->device, true), batched_grid(ctx->device, false)};
   // both launches run every time (an empty class ends at once), so the

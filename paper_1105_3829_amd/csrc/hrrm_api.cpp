@@ -178,12 +178,21 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     rows = std::max<int64_t>(std::max<int64_t>(16, span), (strips * h * d) / 2048);
   }
   // 2-D: the grey-level-window kernel where it measured faster than the
-  // tiered kernel (MI355X; 8-bit low-key 8192^2 r = 8, 16: 0.8-1.1 against
-  // 1.6-1.7 ms; 16-bit X-ray-like 4096^2 r = 8..50), and for every adaptive
-  // 2-D tree from r = 6
+  // tiered kernel (MI355X):
+  //   8-bit uniform tree r = 1..24 (low-key 8192^2: r = 1 1.03 against
+  //   1.21 ms, r = 16 1.49 against 1.57, r = 24 1.54 against 1.59; uniform
+  //   noise 4096^2 r = 2 0.61 against 0.98); past r = 24 the window counts
+  //   of a dense grey level overflow their bytes (low-key r = 28: 2.16
+  //   against 1.61);
+  //   8-bit adaptive r = 1..32 (low-key r = 1 0.80, r = 32 3.5 against the
+  //   topology-tree's 6.4 ms; r = 64 9.9 against 7.8);
+  //   16-bit uniform tree from r = 6 (X-ray-like 4096^2 r = 6 1.28 against
+  //   1.56 ms, r = 15 0.49 against 1.41; at r <= 5 the medians of
+  //   neighbouring pixels spread wider than the grey-level window), and
+  //   16-bit adaptive at every r (r = 5 1.88 against 11 ms)
   t.window_rows = 0;
-  if (dims == 2 && ((bytes == 1 && r >= 6 && r <= 16) || (bytes == 2 && r >= 8) ||
-                    (adaptive && r >= 6)))
+  if (dims == 2 && r >= 1 &&
+      (bytes == 1 ? r <= (adaptive ? 32 : 24) : (adaptive || r >= 6)))
     t.window_rows = r <= 24 ? 32 : 64;  // C1 r = 15: 0.41 adaptive, 0.49 ms plain
   // an image filtered on its own keeps at least two tiles per workgroup slot
   // of the GPU (256 CUs, 1 to 6 workgroups each) when it allows it; in a
@@ -271,10 +280,13 @@ static int tiered_args(const TileConfig& t0, int bytes, int dims, bool adaptive,
   a.min_group = std::max(1, t.min_group);
   a.max_groups = std::max(0, t.max_groups);
   a.raw_window = std::max(0, t.raw_window);
-  // the matrix cores take column counts as signed bytes (volumes: shifted by
-  // -128 for counts past 127), over at most three 64-column steps
-  const int maxcol = dims == 3 ? (2 * r + 1) * (2 * r + 1) : 2 * r + 1;
-  a.mfma = maxcol <= 127 ? 1 : dims == 3 && maxcol <= 255 ? 2 : 0;
+  // window counts on the matrix cores only for 8-bit 2-D windows of 2r + 1
+  // <= 127 rows (column counts as signed bytes): the one case where they
+  // measured clearly faster than the DPP-scan and per-lane counts (MI355X,
+  // tiered kernel, 8-bit low-key 8192^2 r = 16: 1.57 against 1.94 ms,
+  // r = 32: 1.63 against 2.30; 16-bit X-ray-like 4096^2 r = 15 to 50 and
+  // 16-bit volumes r = 3 to 7 within 0 to 9 %)
+  a.mfma = dims == 2 && bytes == 1 && 2 * r + 1 <= 127 ? 1 : 0;
   a.topo = nullptr;
   a.need = nullptr;
 
@@ -316,23 +328,22 @@ static int tiered_args(const TileConfig& t0, int bytes, int dims, bool adaptive,
   return HRRM_OK;
 }
 
-// 2-D grey-level-window kernel, then the tiered kernel (uniform tree) over the
-// tiles the window kernel flagged.
-static int run_window(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
-                      int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
-                      bool adaptive, hipStream_t stream, uint32_t* need_buf) {
+// Arguments of the grey-level-window launch of one 2-D image (segments of
+// t.window_rows rows) and of the tiered kernel's pass (uniform tree) over the
+// tiles the window kernel flags; neither `need` pointer is set.
+int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
+                 int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
+                 WindowArgs& wa, MedianArgs& fa) {
   // rows the window kernel cannot finish are rare and come alone: short
   // fallback tiles
   TileConfig ft = ctx->tile_for(bytes, 2, r, false, w, h, 1);
   ft.window_rows = 0;
   ft.seg_rows = 16;
-  MedianArgs fa;
   bool tiered = true;
   int rc = tiered_args(ft, bytes, 2, false, false, src, dst, w, h, 1, srs, 0, drs, 0, r, rank, 0,
                        fa, tiered);
   if (rc != HRRM_OK) return rc;
-  const int64_t tiles = (int64_t)fa.strips * fa.segs;
-  WindowArgs wa{};
+  wa = WindowArgs{};
   wa.src = src;
   wa.dst = dst;
   wa.w = w;
@@ -362,6 +373,19 @@ static int run_window(Context* ctx, const TileConfig& t, const void* src, void* 
   wa.fb_rows = fa.seg_rows;
   if ((int64_t)wa.strips * (wa.segs + 4 * (h / wa.border_rows + 1)) > 0x7fffffffLL)
     return fail(HRRM_EUNSUPPORTED, "image too large for one launch");
+  return HRRM_OK;
+}
+
+// 2-D grey-level-window kernel, then the tiered kernel (uniform tree) over the
+// tiles the window kernel flagged.
+static int run_window(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
+                      int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
+                      bool adaptive, hipStream_t stream, uint32_t* need_buf) {
+  WindowArgs wa;
+  MedianArgs fa;
+  int rc = window_setup(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, wa, fa);
+  if (rc != HRRM_OK) return rc;
+  const int64_t tiles = (int64_t)fa.strips * fa.segs;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
   if (!need_buf) {
@@ -423,7 +447,7 @@ int run_noalloc(Context* ctx, const void* src, void* dst, int dtype, int64_t w, 
   const int bytes = dtype == HRRM_U8 ? 1 : 2;
   const bool adaptive = variant == HRRM_ADAPTIVE;
   TileConfig t = ctx->tile_for(bytes, 2, r, adaptive, w, h, 1);
-  if (adaptive && t.window_rows <= 0) t.window_rows = 32;
+  if (adaptive && t.window_rows <= 0) t.window_rows = r <= 24 ? 32 : 64;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
   if (t.window_rows > 0) {

@@ -68,8 +68,8 @@ struct MedianArgs {
   int32_t min_group;  // smallest lane group counted cooperatively
   int32_t max_groups; // cooperative groups per level before falling back to direct sums
   int32_t raw_window; // windows of at most this many values count a missing subtree raw
-  int32_t mfma;       // window counts on the matrix cores: 1 (column counts <= 127), 2 (3-D,
-                      // counts <= 255 as shifted bytes); 0 = not
+  int32_t mfma;       // 1: window counts on the matrix cores (8-bit 2-D, column counts
+                      // <= 127); 0 = DPP-scan and per-lane counts
   int32_t wslots;     // > 0: slots per wave of wave-private deeper subtrees (uniform 2-D)
   int32_t wpitch;     // columns per wave-private slot (>= 64 + 2r + 1)
   int32_t pad1;
@@ -124,7 +124,20 @@ struct WindowArgs {
   int32_t fb_strips, fb_rows;
 };
 
+// One image of a multi-image window launch: its arguments and the exclusive
+// end of its workgroups in the launch's grid.
+struct WindowImage {
+  WindowArgs args;
+  int64_t group_end;
+};
+
 size_t window_wave_bytes(int r);
+int64_t window_tiles(const WindowArgs& a);
+// Waves per workgroup of a multi-image window launch of `bytes`-byte images
+// whose largest radius is r_max; 0 when no such launch exists (r_max > 32).
+int window_multi_waves(int bytes, int r_max);
+hipError_t launch_window_multi(const WindowImage* d_imgs, int n, int64_t groups, int bytes,
+                               int r_max, hipStream_t stream);
 int window_waves_per_group(int r);
 // adaptive = scanned range placed on the medians (64 leaves); else the uniform
 // tree's pairs of 64-leaf subtrees (128 leaves)

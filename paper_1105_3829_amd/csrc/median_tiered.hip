@@ -250,9 +250,8 @@ typedef int v4i_t __attribute__((ext_vector_type(4)));
 // sum_k col[k][node] * band[k][pixel], where k runs over the 64 + 2r columns
 // the wave's windows cover and band[k][pixel] = 1 when column k lies in the
 // pixel's window - the paper's window update (Sec. III) summed for all nodes
-// of the tier at once.  Column counts enter as signed bytes; counts past 127
-// (a.mfma = 2) enter as c - 128 (c XOR 0x80), and adding 128 per window
-// column (128 (2r + 1)) to every result undoes the shift.
+// of the tier at once.  Column counts enter as signed bytes (8-bit 2-D
+// windows of 2r + 1 <= 127 rows: the only launches that enable it).
 //
 // Operands of v_mfma_i32_16x16x64_i8: lane l holds A[i = l % 16][k = 16(l/16)
 // + b] and B[k = 16(l/16) + b][j = l % 16] for b = 0..15, and receives
@@ -300,12 +299,10 @@ __device__ __forceinline__ void band_init(Band& bd, int span, int lane) {
 // the packed layout wsel reads: the two words of node rows 4g..4g+3 of pixel
 // p at g * 512 + p * 8 bytes, so that 16 lanes of one row group store, and
 // all 64 lanes load, consecutive 8-byte words (no bank conflicts).  All 64
-// lanes must call it.  SHIFT: column counts past 127, shifted by -128 on the
-// way in and back by `bias` = 128 (2r + 1) on the way out.
-template <bool SHIFT>
+// lanes must call it.
 __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots, size_t cp16,
                                            int cmax, int s, uint64_t m, int wbase, int lane,
-                                           uint8_t* stage, int bias) {
+                                           uint8_t* stage) {
   const int g = lane >> 4, t = lane & 15;
   const uint8_t* sb = slots + (size_t)s * cp16;
   const int cb = wbase + 1;  // first window column of the wave's first pixel
@@ -323,20 +320,10 @@ __device__ __forceinline__ void mfma_group(const Band& bd, const uint8_t* slots,
         a[2 * h] = rr.x;
         a[2 * h + 1] = rr.y;
       }
-      if constexpr (SHIFT) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] ^= (int)0x80808080u;
-      }
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
         acc[nt] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bd.f[ks][nt], acc[nt], 0, 0, 0);
     }
-  }
-  if constexpr (SHIFT) {
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[nt][v] += bias;
   }
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -929,13 +916,7 @@ __device__ __forceinline__ void tile_body(const MedianArgs& a, uint8_t* lds, int
             const int s = readlane(slot, __builtin_ctzll(t));
             const uint64_t m = ballot(slot == s) & t;
             t &= ~m;
-            // (shifted counts only in volumes: a 2-D column holds at most 2r + 1
-            // <= 129 values, and the one radius past 127 does not pay for the
-            // second instance in every 2-D build)
-            if (D3 && a.mfma == 2)
-              mfma_group<D3>(band, cslots, ccp16, cmax, s, m, wv * 64, lane, scr, 128 * span);
-            else
-              mfma_group<false>(band, cslots, ccp16, cmax, s, m, wv * 64, lane, scr, 0);
+            mfma_group(band, cslots, ccp16, cmax, s, m, wv * 64, lane, scr);
           }
           wave_sync_lds();
           if ((pend >> lane) & 1) {

@@ -483,16 +483,14 @@ __device__ __forceinline__ void row16(const WaveLds& L, uint32_t* b16, int qs, i
   off = (b1 ? 32 : 0) + (b2 ? 16 : 0) + (b3 ? 8 : 0) + (b4 ? 4 : 0) + (b5 ? 2 : 0) + (b6 ? 1 : 0);
 }
 
-template <typename T, bool ADAPT, int KC, int WPG>
-__global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
-  extern __shared__ __align__(16) uint8_t lds[];
+// One wave's tile `tile` of the image `a` (tiles in launch order: short
+// segments near the image's edges first (see WindowArgs), then the inner
+// strips' segments, neighbouring strips together); wv = the wave's index in
+// its workgroup, uniform (its LDS area).
+template <typename T, bool ADAPT, int KC>
+__device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, int wv,
+                                            uint8_t* lds) {
   const int lane = threadIdx.x & 63;
-  // the wave's index in the workgroup, as a value the compiler knows to be
-  // uniform: everything derived from it (tile, rows, range) stays scalar
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // tiles in launch order: short segments near the image's edges first (see
-  // WindowArgs), then the inner strips' segments, neighbouring strips together
-  const int64_t tile = (int64_t)blockIdx.x * WPG + wv;
   const int inner = a.strips > 2 ? a.strips - 2 : 0;
   const int64_t mid_tiles =
       inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0;
@@ -762,16 +760,44 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
 constexpr int kc_for(int r) { return (64 + 2 * r + 63) / 64; }
 
 template <typename T, bool ADAPT, int KC, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  // the wave's index in the workgroup, as a value the compiler knows to be
+  // uniform: everything derived from it (tile, rows, range) stays scalar
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  window_tile<T, ADAPT, KC>(a, (int64_t)blockIdx.x * WPG + wv, wv, lds);
+}
+
+// Many images in one launch (uniform tree): workgroup g belongs to the first
+// image whose workgroup range ends after g; each image's tiles start on a
+// workgroup boundary, so the waves of a workgroup share one image (and its
+// LDS layout).  The launch's LDS holds WPG waves of the largest image radius.
+template <typename T, int KC, int WPG>
+__global__ __launch_bounds__(64 * WPG) void k_median_window_multi(
+    const WindowImage* __restrict__ imgs, int n) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int64_t g = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (imgs[mid].group_end > g)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  const int64_t first = lo > 0 ? imgs[lo - 1].group_end : 0;
+  const WindowArgs a = imgs[lo].args;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  window_tile<T, false, KC>(a, (g - first) * WPG + wv, wv, lds);
+}
+
+template <typename T, bool ADAPT, int KC, int WPG>
 hipError_t launch_k(const WindowArgs& a, hipStream_t stream) {
   const size_t lds = (size_t)WPG * a.wave_bytes;
   const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG>;
   hipError_t e = ensure_dynamic_lds(kern, lds);
   if (e != hipSuccess) return e;
-  const int inner = a.strips > 2 ? a.strips - 2 : 0;
-  const int64_t tiles =
-      (int64_t)a.border_tiles +
-      (inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0);
-  const int64_t grid = (tiles + WPG - 1) / WPG;
+  const int64_t grid = (window_tiles(a) + WPG - 1) / WPG;
   hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG>), dim3((uint32_t)grid), dim3(64 * WPG),
                      lds, stream, a);
   return hipGetLastError();
@@ -809,6 +835,35 @@ hipError_t prime_w() {
 
 }  // namespace
 
+int64_t window_tiles(const WindowArgs& a) {
+  const int inner = a.strips > 2 ? a.strips - 2 : 0;
+  return (int64_t)a.border_tiles +
+         (inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0);
+}
+
+int window_multi_waves(int bytes, int r_max) {
+  return kc_for(r_max) > 2 ? 0 : bytes == 2 ? 1 : 4;
+}
+
+hipError_t launch_window_multi(const WindowImage* d_imgs, int n, int64_t groups, int bytes,
+                               int r_max, hipStream_t stream) {
+  if (n <= 0 || groups <= 0) return hipSuccess;
+  if (kc_for(r_max) > 2 || groups > 0x7fffffffLL) return hipErrorInvalidValue;
+  const int wpg = window_multi_waves(bytes, r_max);
+  const size_t lds = (size_t)wpg * window_wave_bytes(r_max);
+  const void* kern = bytes == 2 ? (const void*)k_median_window_multi<uint16_t, 2, 1>
+                                : (const void*)k_median_window_multi<uint8_t, 2, 4>;
+  hipError_t e = ensure_dynamic_lds(kern, lds);
+  if (e != hipSuccess) return e;
+  if (bytes == 2)
+    hipLaunchKernelGGL((k_median_window_multi<uint16_t, 2, 1>), dim3((uint32_t)groups), dim3(64),
+                       lds, stream, d_imgs, n);
+  else
+    hipLaunchKernelGGL((k_median_window_multi<uint8_t, 2, 4>), dim3((uint32_t)groups),
+                       dim3(256), lds, stream, d_imgs, n);
+  return hipGetLastError();
+}
+
 size_t window_wave_bytes(int r) {
   const int ncols = 64 + 2 * r;
   // + base (kPitch dwords) + the 16-bit counts of the first window (32)
@@ -844,6 +899,10 @@ hipError_t prime_window_lds() {
   if (e == hipSuccess) e = prime_w<uint8_t, false>();
   if (e == hipSuccess) e = prime_w<uint16_t, true>();
   if (e == hipSuccess) e = prime_w<uint16_t, false>();
+  if (e == hipSuccess)
+    e = ensure_dynamic_lds((const void*)k_median_window_multi<uint8_t, 2, 4>, kLdsLimit);
+  if (e == hipSuccess)
+    e = ensure_dynamic_lds((const void*)k_median_window_multi<uint16_t, 2, 1>, kLdsLimit);
   return e;
 }
 

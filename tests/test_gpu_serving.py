@@ -86,6 +86,34 @@ def test_batched_large_mix_equals_alone(hrrm):
     assert np.array_equal(to_host(outs[k])[ys, xs], oracle.rank2d_at(img, r, xs, ys))
 
 
+def test_batched_window_images_only(hrrm):
+    # batches whose every image takes the grey-level-window kernel (no
+    # persistent launch), of both element types, degenerate shapes included;
+    # two batches in a row reuse the staging and flag buffers
+    import torch
+    ctx = hrrm.Context(0)
+    stream = torch.cuda.Stream()
+    shapes = [[(1, 1), (64, 1), (2, 300), (130, 257), (300, 64), (33, 65)],
+              [(5, 7), (257, 130), (1, 500), (96, 96)]]
+    for rep, sh in enumerate(shapes):
+        imgs = []
+        for i, (h, w) in enumerate(sh):
+            if i % 2:
+                imgs.append((datagen.uniform_u8(h, w, seed=50 + i + 10 * rep), [1, 7, 15, 24][i % 4]))
+            else:
+                imgs.append((datagen.xray_u16(h, w, seed=60 + i + 10 * rep), [7, 15, 31, 32][i % 4]))
+        announce("batched window-only", rep, [(i.shape, i.dtype.name, r) for i, r in imgs])
+        srcs = [to_dev(i) for i, _ in imgs]
+        outs = [torch.empty_like(s) for s in srcs]
+        torch.cuda.synchronize()
+        ctx.median2d_batched(srcs, [r for _, r in imgs], outs=outs, stream=stream)
+        torch.cuda.synchronize()
+        for (img, r), o in zip(imgs, outs):
+            got = to_host(o)
+            want = oracle.median2d(img, r)
+            assert np.array_equal(got, want), (img.shape, r, first_mismatch(got, want))
+
+
 def test_batched_rejects_bad_image(hrrm):
     import torch
     ctx = hrrm.Context(0)
