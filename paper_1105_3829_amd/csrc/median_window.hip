@@ -542,14 +542,20 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
 
   // scanned range: dwords [q0, q0 + sq) of the leaves [bc, bc + 128);
   // adaptive trees scan 16 dwords placed on the medians, widening to all 32
-  // for rows whose medians spread wider; the uniform tree scans all 32
+  // for rows whose medians spread wider; the uniform tree scans both of its
+  // 64-leaf subtrees, or (8-bit) only one of them from a row whose medians
+  // lie well inside it until a median leaves it.  (16-bit: the medians of a
+  // row at r = 10..31 rarely fit one subtree, and the second code path alone
+  // measured 8 % slower; 8-bit low-key 8192^2 r = 8: 1.13 -> 0.89 ms.)
+  constexpr bool kNarrowPlain = sizeof(T) == 1;
   int bc = 0, q0 = 0;
-  bool wide = !ADAPT;
+  bool wide = true;
   auto place = [&](int m) {
     if (!ADAPT) {  // two 64-leaf subtrees of the uniform tree, m in the middle half
       bc = (m & ~63) - ((m & 63) < 32 ? 64 : 0);
       bc = bc < 0 ? 0 : bc;
       q0 = 0;
+      wide = true;
     } else if (wide) {
       bc = (m - 64) & ~15;
       bc = bc < 0 ? 0 : bc;
@@ -601,7 +607,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     bool have = false, done = true, moved = false;
     for (int tries = 0;; ++tries) {
       RowOut o;
-      if (ADAPT && !wide)
+      if (!wide)
         o = row_medians<16>(L, q0, lane, r2, a.n, rank, live);
       else
         o = row_medians<kBinQ>(L, q0, lane, r2, a.n, rank, live);
@@ -615,7 +621,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         // a leaf count passed 255: count the scanned leaves again with
         // 16-bit fields, 64 leaves at a time
         int below = o.lo;
-        for (int qs = q0; qs < q0 + (ADAPT && !wide ? 16 : kBinQ); qs += 16) {
+        for (int qs = q0; qs < q0 + (!wide ? 16 : kBinQ); qs += 16) {
           int off16, cnt16;
           bool ok16;
           row16(L, L.base + kPitch, qs, lane, r2, rank, below, off16, ok16, cnt16);
@@ -634,7 +640,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         done = false;
         break;
       }
-      if (ADAPT && !wide) {  // scan all 128 leaves
+      if (!wide) {  // scan all 128 leaves
         retarget<KC>(L, ncols, r2, q0, 16, 0, kBinQ, lane);
         q0 = 0;
         wide = true;
@@ -715,6 +721,16 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
           rebuilt = true;
         }
       }
+    } else if (kNarrowPlain && !wide) {
+      // one subtree scanned: it stays until a median leaves it (a pass that
+      // misses scans both again)
+    } else if (kNarrowPlain && (!ballot(live && (off < kMargin || off >= 64 - kMargin)) ||
+                                !ballot(live && (off < 64 + kMargin || off >= 128 - kMargin)))) {
+      // the row's medians lie well inside one subtree: scan only that one
+      const int q1 = ballot(live && off >= 64) ? 16 : 0;
+      retarget<KC>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
+      q0 = q1;
+      wide = false;
     } else {
       // move the pair of subtrees by one subtree
       const bool near_lo = ballot(live && off < kMargin) != 0;

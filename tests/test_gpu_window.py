@@ -65,10 +65,34 @@ def test_u16_xray(hrrm, ctx, variant, r):
 
 
 @pytest.mark.parametrize("variant", ["plain", "adaptive"])
-@pytest.mark.parametrize("r", [6, 8, 12, 16])
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 6, 8, 12, 16, 24, 32])
 def test_u8_lowkey(hrrm, ctx, variant, r):
     img = datagen.lowkey_u8(140, 290, seed=320 + r)
     _check(hrrm, ctx, "lowkey", img, r, variant)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 5])
+def test_small_radii(hrrm, ctx, r):
+    # small windows: 8-bit uniform noise (a row's medians spread over most of
+    # the grey range: passes moved and rebuilt, rows left to the tiered
+    # kernel) and the 16-bit X-ray-like image, both variants
+    img8 = datagen.uniform_u8(90, 300, seed=330 + r)
+    img16 = datagen.xray_u16(90, 300, seed=335 + r)
+    for variant in ("plain", "adaptive"):
+        _check(hrrm, ctx, "noise u8", img8, r, variant)
+        _check(hrrm, ctx, "xray small r", img16, r, variant)
+
+
+@pytest.mark.parametrize("r", [3, 9, 20])
+def test_u8_subtree_crossings(hrrm, ctx, r):
+    # 8-bit gradients whose row medians drift across the 64-level subtree
+    # boundaries: the uniform tree's scan narrows to one subtree and widens
+    # again on a miss; a steep ramp also spreads one row over both subtrees
+    y, x = np.mgrid[0:160, 0:300]
+    for slope in (0.1, 0.5):
+        img = np.clip(40 + slope * x + 0.3 * y + (x * 7 + y * 13) % 5, 0, 255).astype(np.uint8)
+        for variant in ("plain", "adaptive"):
+            _check(hrrm, ctx, "u8 ramp %.1f" % slope, img, r, variant)
 
 
 @pytest.mark.parametrize("r", [6, 15, 33])
