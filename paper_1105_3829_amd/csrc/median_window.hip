@@ -549,7 +549,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   // measured 8 % slower; 8-bit low-key 8192^2 r = 8: 1.13 -> 0.89 ms.)
   constexpr bool kNarrowPlain = sizeof(T) == 1;
   int bc = 0, q0 = 0;
-  bool wide = true;
+  bool wide = !ADAPT;  // adaptive trees start on 16 dwords
   auto place = [&](int m) {
     if (!ADAPT) {  // two 64-leaf subtrees of the uniform tree, m in the middle half
       bc = (m & ~63) - ((m & 63) < 32 ? 64 : 0);
@@ -696,29 +696,32 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         wide = false;
       }
     } else if (ADAPT) {
+      // (the shift tests only for rows with a median near an edge that can move)
       const int bs = bc + 4 * q0;
-      const bool near_lo = ballot(live && off < kMargin) != 0;
-      const bool near_hi = ballot(live && off >= 64 - kMargin) != 0;
-      // shift by 16 leaves when the far side keeps its margin afterwards
-      const bool room_lo = ballot(live && off >= 64 - kMargin - 16) == 0;
-      const bool room_hi = ballot(live && off < kMargin + 16) == 0;
-      if (near_lo && room_lo && bs > 0) {
-        if (q0 >= 4) {
-          retarget<KC>(L, ncols, r2, q0, 16, q0 - 4, 16, lane);
-          q0 -= 4;
-        } else {
-          place(bs + 32 - 16);
-          build(y + 1);
-          rebuilt = true;
-        }
-      } else if (near_hi && room_hi && bs + 64 <= maxv) {
-        if (q0 + 4 <= kBinQ - 16) {
-          retarget<KC>(L, ncols, r2, q0, 16, q0 + 4, 16, lane);
-          q0 += 4;
-        } else {
-          place(bs + 32 + 16);
-          build(y + 1);
-          rebuilt = true;
+      if (ballot(live && ((bs > 0 && off < kMargin) || (bs + 64 <= maxv && off >= 64 - kMargin)))) {
+        const bool near_lo = ballot(live && off < kMargin) != 0;
+        const bool near_hi = ballot(live && off >= 64 - kMargin) != 0;
+        // shift by 16 leaves when the far side keeps its margin afterwards
+        const bool room_lo = ballot(live && off >= 64 - kMargin - 16) == 0;
+        const bool room_hi = ballot(live && off < kMargin + 16) == 0;
+        if (near_lo && room_lo && bs > 0) {
+          if (q0 >= 4) {
+            retarget<KC>(L, ncols, r2, q0, 16, q0 - 4, 16, lane);
+            q0 -= 4;
+          } else {
+            place(bs + 32 - 16);
+            build(y + 1);
+            rebuilt = true;
+          }
+        } else if (near_hi && room_hi && bs + 64 <= maxv) {
+          if (q0 + 4 <= kBinQ - 16) {
+            retarget<KC>(L, ncols, r2, q0, 16, q0 + 4, 16, lane);
+            q0 += 4;
+          } else {
+            place(bs + 32 + 16);
+            build(y + 1);
+            rebuilt = true;
+          }
         }
       }
     } else if (kNarrowPlain && !wide) {
