@@ -53,10 +53,14 @@ typedef enum { HRRM_U8 = 1, HRRM_U16 = 2 } hrrm_dtype;
 /* Tree topology and window-update form.  PLAIN: the uniform
  * interval-occurrences tree (Sec. III), each split halves its interval,
  * height = bit depth, window counts built on demand for the nodes the descent
- * visits.  ADAPTIVE: the adaptive tree of Sec. III-C, split so that both
- * children are visited about equally often, estimated from the 1:1 mix of the
- * input's global histogram and the global histogram of its running (box) mean;
- * frequent grey values get short paths.  FULL_UPDATE: the uniform tree with the
+ * visits.  ADAPTIVE: a tree shaped by an estimate of where the medians lie
+ * (Sec. III-C), so that the descent skips the levels above them.  2-D images
+ * (8-bit up to r = 32, 16-bit at every r): per strip of 64 columns, a 64-leaf
+ * range placed on the previous rows' medians, reached by two short paths
+ * ("below" / "above") from the root.  Volumes and wider 8-bit windows: split
+ * so that both children are visited about equally often, estimated from the
+ * 1:1 mix of the input's global histogram and the global histogram of its
+ * running (box) mean; frequent grey values get short paths.  FULL_UPDATE: the uniform tree with the
  * unconditional update of the entire window tree at every pixel (Sec. III:
  * strictly constant work per pixel, one update per node), 8-bit data only
  * (EUNSUPPORTED for 16-bit).  All give identical output. */
@@ -186,12 +190,16 @@ typedef struct {
   int32_t r;
 } hrrm_image;
 
-/* Filter `count` independent 2-D images (PLAIN median) in ONE persistent
- * launch: workgroups pull tiles of all images from a device work counter, with
- * the tile shape of each image taken from the context's tile table (see
- * hrrm_autotune).  `images` is a HOST array; it is copied into a device
- * descriptor ring owned by the context.  The launch is captured once per
- * (context, stream) into a HIP graph and replayed for later batches.
+/* Filter `count` independent 2-D images (PLAIN median) with a few launches
+ * for the whole batch: images whose tile configuration picks the
+ * grey-level-window kernel (r <= 32) run as one multi-image launch per
+ * element type (each image's strips in one grid) followed by one pass per
+ * image over the tiles that launch flagged; all others run in ONE persistent
+ * launch whose workgroups pull tiles of all images from a device work counter.
+ * The tile shape of each image comes from the context's tile table (see
+ * hrrm_autotune).  `images` is a HOST array; it is copied into device
+ * descriptor buffers owned by the context.  The persistent launch is captured
+ * once per (context, stream) into a HIP graph and replayed for later batches.
  * Errors: as hrrm_median2d for any image; EINVAL if count < 0 or
  * count > hrrm_batch_capacity(). */
 int hrrm_median2d_batched(hrrm_ctx ctx, const hrrm_image* images, int32_t count,
