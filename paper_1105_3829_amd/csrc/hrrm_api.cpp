@@ -333,7 +333,7 @@ static int tiered_args(const TileConfig& t0, int bytes, int dims, bool adaptive,
 // tiles the window kernel flags; neither `need` pointer is set.
 int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
                  int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
-                 WindowArgs& wa, MedianArgs& fa) {
+                 WindowArgs& wa, MedianArgs& fa, bool alone) {
   // rows the window kernel cannot finish are rare and come alone: short
   // fallback tiles
   TileConfig ft = ctx->tile_for(bytes, 2, r, false, w, h, 1);
@@ -353,8 +353,16 @@ int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, 
   wa.rank = rank;
   wa.r = r;
   wa.n = (2 * r + 1) * (2 * r + 1);
-  wa.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(t.window_rows, h));
   wa.strips = (int32_t)((w + 63) / 64);
+  int64_t seg = t.window_rows;
+  // waves the GPU holds at once
+  const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(bytes, r);
+  if (alone && seg > 8 && (int64_t)wa.strips * ((h + seg - 1) / seg) < 2 * slots) {
+    // too few segments for two generations of waves: shorter ones (C1-like
+    // 1024^2 r = 15: 8-row segments finish about 3x sooner than 32-row ones)
+    seg = std::max<int64_t>(8, std::min<int64_t>(seg, (int64_t)wa.strips * h / (2 * slots)));
+  }
+  wa.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(seg, h));
   wa.segs = (int32_t)((h + wa.seg_rows - 1) / wa.seg_rows);
   wa.border_rows = std::max<int32_t>(1, std::min<int32_t>(wa.seg_rows, 8));
   {
@@ -363,6 +371,19 @@ int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, 
     const int64_t bot_start = std::max<int64_t>(top_end, h - wa.seg_rows);
     wa.top_end = (int32_t)top_end;
     wa.bot_start = (int32_t)bot_start;
+    // the last generation of inner-strip segments at half height, so that
+    // the launch's last waves end together (u16 4096^2 r = 15: the 32-row
+    // segments' last generation started at 336 of 473 us; 0.48 -> 0.465 ms,
+    // r = 7 0.82 -> 0.77, r = 31 0.63 -> 0.60).  Past r = 32 a segment's
+    // build of 2r + 1 rows costs more than the shorter tail saves (r = 50
+    // 1.20 -> 1.27 ms).
+    wa.tail_rows = std::max<int32_t>(1, wa.seg_rows / 2);
+    int64_t tail_start = bot_start;
+    if (alone && inner > 0 && wa.seg_rows >= 16 && r <= 32) {
+      const int64_t tail_segs = (slots + inner - 1) / inner;
+      tail_start = std::max<int64_t>(top_end, bot_start - tail_segs * wa.tail_rows);
+    }
+    wa.tail_start = (int32_t)tail_start;
     wa.side_tiles = (int32_t)((wa.strips > 1 ? 2 : 1) * ((h + br - 1) / br));
     wa.top_tiles = (int32_t)(inner * ((top_end + br - 1) / br));
     wa.border_tiles =
@@ -383,7 +404,7 @@ static int run_window(Context* ctx, const TileConfig& t, const void* src, void* 
                       bool adaptive, hipStream_t stream, uint32_t* need_buf) {
   WindowArgs wa;
   MedianArgs fa;
-  int rc = window_setup(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, wa, fa);
+  int rc = window_setup(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, wa, fa, true);
   if (rc != HRRM_OK) return rc;
   const int64_t tiles = (int64_t)fa.strips * fa.segs;
   hipError_t e = hipSetDevice(ctx->device);
@@ -464,6 +485,17 @@ int run_noalloc(Context* ctx, const void* src, void* dst, int dtype, int64_t w, 
   e = launch_median(a, bytes, 2, false, tiered, false, stream);
   if (e != hipSuccess) return fail_hip(e, "median kernel launch");
   return HRRM_OK;
+}
+
+int Context::cu_count() {
+  if (cus <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    cus = n;
+  }
+  return cus;
 }
 
 int Context::ensure_need(int64_t tiles, hipStream_t stream, uint32_t** out) {

@@ -29,6 +29,8 @@ struct BatchStream {
 
 struct Context {
   int device = 0;
+  int cus = 0;  // compute units of the device (0: not yet queried)
+  int cu_count();
   // adaptive topology workspace (histograms, prefix sums, box sums, frontier)
   void* topo_ws = nullptr;
   size_t topo_ws_bytes = 0;
@@ -76,9 +78,12 @@ int load_tuning(Context* c, const char* path);
 int save_tuning(const Context* c, const char* path);
 int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t stream,
                 bool use_graph);
+// alone: the image has the GPU to itself (segments shortened until it fills
+// the GPU, and the launch's last generation of waves in half-height
+// segments); in a batch the other images fill it
 int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
                  int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
-                 WindowArgs& wa, MedianArgs& fa);
+                 WindowArgs& wa, MedianArgs& fa, bool alone);
 // est / est_rs: optional estimate image for the adaptive topology (2-D)
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
                int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,

@@ -117,8 +117,11 @@ struct WindowArgs {
   // run first, in short segments of border_rows rows: the first and last
   // strip over all rows (side_tiles tiles), then the other strips' rows
   // [0, top_end) (top_tiles tiles) and [bot_start, h); the rest of those
-  // strips, rows [top_end, bot_start), follows in segments of seg_rows rows.
+  // strips follows, rows [top_end, tail_start) in segments of seg_rows rows,
+  // then rows [tail_start, bot_start) in segments of tail_rows rows (the
+  // launch's last generation of waves, shorter so that it ends together).
   int32_t border_rows, border_tiles, side_tiles, top_tiles, top_end, bot_start;
+  int32_t tail_start, tail_rows;
   int32_t wave_bytes;  // LDS bytes of one wave
   uint32_t* need;
   int32_t fb_strips, fb_rows;
@@ -132,6 +135,8 @@ struct WindowImage {
 };
 
 size_t window_wave_bytes(int r);
+// Waves of one window launch (element size `bytes`, radius r) that fit a CU.
+int window_waves_per_cu(int bytes, int r);
 int64_t window_tiles(const WindowArgs& a);
 // Waves per workgroup of a multi-image window launch of `bytes`-byte images
 // whose largest radius is r_max; 0 when no such launch exists (r_max > 32).

@@ -493,8 +493,10 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   const int lane = threadIdx.x & 63;
   const int inner = a.strips > 2 ? a.strips - 2 : 0;
   const int64_t mid_tiles =
-      inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0;
-  if (tile >= (int64_t)a.border_tiles + mid_tiles) return;
+      inner ? (int64_t)inner * ((a.tail_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0;
+  const int64_t tail_tiles =
+      inner ? (int64_t)inner * ((a.bot_start - a.tail_start + a.tail_rows - 1) / a.tail_rows) : 0;
+  if (tile >= (int64_t)a.border_tiles + mid_tiles + tail_tiles) return;
   int strip, y0, y1;
   if (tile < a.side_tiles) {
     const int sides = a.strips > 1 ? 2 : 1;
@@ -511,11 +513,16 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     strip = 1 + j % inner;
     y0 = a.bot_start + (j / inner) * a.border_rows;
     y1 = y0 + a.border_rows;
-  } else {
+  } else if (tile < a.border_tiles + mid_tiles) {
     const int64_t j = tile - a.border_tiles;
     strip = 1 + (int)(j % inner);
     y0 = a.top_end + (int)(j / inner) * a.seg_rows;
-    y1 = y0 + a.seg_rows < a.bot_start ? y0 + a.seg_rows : a.bot_start;
+    y1 = y0 + a.seg_rows < a.tail_start ? y0 + a.seg_rows : a.tail_start;
+  } else {
+    const int64_t j = tile - a.border_tiles - mid_tiles;
+    strip = 1 + (int)(j % inner);
+    y0 = a.tail_start + (int)(j / inner) * a.tail_rows;
+    y1 = y0 + a.tail_rows < a.bot_start ? y0 + a.tail_rows : a.bot_start;
   }
   const T* __restrict__ src = (const T*)a.src;
   T* __restrict__ dst = (T*)a.dst;
@@ -855,9 +862,18 @@ hipError_t prime_w() {
 }  // namespace
 
 int64_t window_tiles(const WindowArgs& a) {
-  const int inner = a.strips > 2 ? a.strips - 2 : 0;
-  return (int64_t)a.border_tiles +
-         (inner ? (int64_t)inner * ((a.bot_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0);
+  const int64_t inner = a.strips > 2 ? a.strips - 2 : 0;
+  if (!inner) return a.border_tiles;
+  return (int64_t)a.border_tiles + inner * ((a.tail_start - a.top_end + a.seg_rows - 1) / a.seg_rows) +
+         inner * ((a.bot_start - a.tail_start + a.tail_rows - 1) / a.tail_rows);
+}
+
+int window_waves_per_cu(int bytes, int r) {
+  const int wpg = kc_for(r) <= 2 ? (bytes == 2 ? 1 : 4) : window_waves_per_group(r);
+  const size_t per = (size_t)wpg * window_wave_bytes(r);
+  const int groups = (int)((size_t)kLdsLimit / per);
+  const int waves = groups * wpg;
+  return waves < 32 ? (waves > 0 ? waves : 1) : 32;
 }
 
 int window_multi_waves(int bytes, int r_max) {

@@ -114,6 +114,60 @@ def test_batched_window_images_only(hrrm):
             assert np.array_equal(got, want), (img.shape, r, first_mismatch(got, want))
 
 
+def test_batched_large_images_run_alone(hrrm):
+    # images large enough to fill the GPU on their own run as single launches
+    # inside a batch (window and tiered kernels), the others are packed; every
+    # output equals the image filtered alone, and sampled pixels the oracle
+    import torch
+    ctx = hrrm.Context(0)
+    g = np.random.default_rng(12)
+    imgs = [(datagen.xray_u16(2048, 4096, seed=90), 15), (datagen.uniform_u8(3000, 3000, seed=91), 3),
+            (datagen.xray_u16(1024, 4096, seed=92), 2), (datagen.xray_u16(300, 500, seed=93), 15),
+            (datagen.uniform_u8(200, 700, seed=94), 31), (datagen.xray_u16(100, 90, seed=95), 1)]
+    announce("batched solo + packed", [(i.shape, i.dtype.name, r) for i, r in imgs])
+    srcs = [to_dev(i) for i, _ in imgs]
+    outs = [torch.empty_like(s) for s in srcs]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(2):  # twice: the flag buffers are reused
+        ctx.median2d_batched(srcs, [r for _, r in imgs], outs=outs, stream=stream)
+        torch.cuda.synchronize()
+        for (img, r), s, o in zip(imgs, srcs, outs):
+            alone = to_host(ctx.median2d(s, r))
+            assert np.array_equal(to_host(o), alone), (img.shape, r)
+    for (img, r), o in zip(imgs, outs):
+        ys = g.integers(0, img.shape[0], 500)
+        xs = g.integers(0, img.shape[1], 500)
+        assert np.array_equal(to_host(o)[ys, xs], oracle.rank2d_at(img, r, xs, ys)), (img.shape, r)
+
+
+def test_batched_persistent_launch(hrrm):
+    # enough small images of the tiered kernel's radii (16-bit r <= 3, 8-bit
+    # r = 31, r = 0) that the batch packs them into the persistent launch
+    import torch
+    ctx = hrrm.Context(0)
+    g = np.random.default_rng(21)
+    imgs = []
+    for i in range(24):
+        h, w = int(g.integers(1, 260)), int(g.integers(1, 300))
+        if i % 3 == 2:
+            imgs.append((datagen.uniform_u8(h, w, seed=700 + i), int(g.choice([0, 31]))))
+        else:
+            imgs.append((datagen.xray_u16(h, w, seed=700 + i), int(g.choice([0, 1, 2, 3]))))
+    announce("batched persistent", [(i.shape, i.dtype.name, r) for i, r in imgs])
+    srcs = [to_dev(i) for i, _ in imgs]
+    outs = [torch.empty_like(s) for s in srcs]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(2):  # graph replay
+        ctx.median2d_batched(srcs, [r for _, r in imgs], outs=outs, stream=stream)
+        torch.cuda.synchronize()
+        for (img, r), o in zip(imgs, outs):
+            got = to_host(o)
+            want = oracle.median2d(img, r)
+            assert np.array_equal(got, want), (img.shape, r, first_mismatch(got, want))
+
+
 def test_batched_rejects_bad_image(hrrm):
     import torch
     ctx = hrrm.Context(0)
