@@ -162,7 +162,7 @@ def measure_peaks():
 
 
 def serving(seconds: float, warmup_s: float = 0.5, rate: float = 2000.0, per_image: bool = False,
-            pools=None):
+            pools=None, sides=(256, 4096)):
     """Replay the seeded Poisson request trace against the continuous-batching
     server; latency = completion - scheduled arrival (upload included, output
     left on the device), throughput = output Mpix completed per second inside
@@ -170,7 +170,8 @@ def serving(seconds: float, warmup_s: float = 0.5, rate: float = 2000.0, per_ima
     import numpy as np
     import paper_1105_3829_amd as hrrm
     from paper_1105_3829_amd import datagen
-    trace = datagen.serving_trace(duration_s=warmup_s + seconds, rate_hz=rate, seed=4)
+    trace = datagen.serving_trace(duration_s=warmup_s + seconds, rate_hz=rate, seed=4,
+                                  min_side=sides[0], max_side=sides[1])
     ctx = hrrm.context(0)
     srv = hrrm.Server(ctx, 48 << 30, max_inflight=1 << 14, max_queue=1 << 20, per_image=per_image)
     t0 = srv.now() + 0.05
@@ -240,16 +241,17 @@ def serving_pools():
     return {"u16": u16, "u8": u8}
 
 
-def serving_ladder(pools, rates, seconds):
+def serving_ladder(pools, rates, seconds, sides=(256, 4096)):
     """Each mode at increasing offered rates: the highest rate whose queue is
     stable with p99 latency within SERVING_SLO_MS is the mode's capacity."""
-    out = {"slo_p99_ms": SERVING_SLO_MS, "seconds_per_rate": seconds, "rates": list(rates)}
+    out = {"slo_p99_ms": SERVING_SLO_MS, "seconds_per_rate": seconds, "rates": list(rates),
+           "sides": list(sides)}
     for per_image in (False, True):
         mode = "per_image" if per_image else "batched"
         runs = []
         best = None
         for rate in rates:
-            r = serving(seconds, rate=rate, per_image=per_image, pools=pools)
+            r = serving(seconds, rate=rate, per_image=per_image, pools=pools, sides=sides)
             runs.append(r)
             if r["queue_stable"] and r["p99_ms"] <= SERVING_SLO_MS:
                 best = r
@@ -390,6 +392,8 @@ def main():
     ap.add_argument("--ladder-rates", default="2000,2500,3000,3500,4000,4500,5000",
                     help="offered rates of the serving ladder (empty = skip it)")
     ap.add_argument("--ladder-seconds", type=float, default=2.0)
+    ap.add_argument("--small-ladder-rates", default="4000,8000,12000,16000,24000,32000,48000",
+                    help="offered rates of the small-image serving ladder (empty = skip it)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -480,6 +484,12 @@ def main():
         rates = [float(x) for x in args.ladder_rates.split(",") if x.strip()]
         if rates:
             res["serving"]["ladder"] = serving_ladder(pools, rates, args.ladder_seconds)
+        rates = [float(x) for x in args.small_ladder_rates.split(",") if x.strip()]
+        if rates:
+            # the same mix of types and radii with small images (W, H ~
+            # U{64..512}), where one launch per image cannot fill the GPU
+            res["serving"]["ladder_small"] = serving_ladder(pools, rates, args.ladder_seconds,
+                                                            sides=(64, 512))
     if not args.no_cpu_baseline:
         print("cpu baseline: timing the oracle", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(img, args.r)

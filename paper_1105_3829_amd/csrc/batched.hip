@@ -52,14 +52,16 @@ BatchStream* Context::batch_for(hipStream_t s) {
     if (b.stream == s) return &b;
   BatchStream b{};
   b.stream = s;
-  if (hipMalloc(&b.d_buf, kBatchBytes) != hipSuccess) return nullptr;
-  if (hipHostMalloc(&b.h_stage, kBatchBytes, hipHostMallocDefault) != hipSuccess) {
-    (void)hipFree(b.d_buf);
-    return nullptr;
-  }
-  if (hipEventCreateWithFlags(&b.staged, hipEventDisableTiming) != hipSuccess) {
-    (void)hipFree(b.d_buf);
-    (void)hipHostFree(b.h_stage);
+  bool ok = hipMalloc(&b.d_buf, kBatchBytes) == hipSuccess;
+  for (int k = 0; ok && k < kStages; ++k)
+    ok = hipHostMalloc(&b.h_stage[k], kBatchBytes, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&b.staged[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    if (b.d_buf) (void)hipFree(b.d_buf);
+    for (int k = 0; k < kStages; ++k) {
+      if (b.h_stage[k]) (void)hipHostFree(b.h_stage[k]);
+      if (b.staged[k]) (void)hipEventDestroy(b.staged[k]);
+    }
     return nullptr;
   }
   batch.push_back(b);
@@ -68,12 +70,15 @@ BatchStream* Context::batch_for(hipStream_t s) {
 
 void Context::release_batch() {
   for (auto& b : batch) {
-    if (b.pending) (void)hipEventSynchronize(b.staged);
+    for (int k = 0; k < kStages; ++k)
+      if (b.pending[k]) (void)hipEventSynchronize(b.staged[k]);
     if (b.exec) (void)hipGraphExecDestroy(b.exec);
     if (b.graph) (void)hipGraphDestroy(b.graph);
-    if (b.staged) (void)hipEventDestroy(b.staged);
+    for (int k = 0; k < kStages; ++k) {
+      if (b.staged[k]) (void)hipEventDestroy(b.staged[k]);
+      if (b.h_stage[k]) (void)hipHostFree(b.h_stage[k]);
+    }
     if (b.d_buf) (void)hipFree(b.d_buf);
-    if (b.h_stage) (void)hipHostFree(b.h_stage);
   }
   batch.clear();
 }
@@ -297,13 +302,18 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
   int32_t* d_hdr[2] = {(int32_t*)(base + 64), (int32_t*)(base + 68)};
   const BatchImage* d_imgs[2] = {(const BatchImage*)(base + kDescOffset),
                                  (const BatchImage*)(base + kDescOffset + kClassBytes)};
-  if (bs->pending) {
-    e = hipEventSynchronize(bs->staged);
+  // the staging copies are used in turn, so the host waits only for the
+  // upload of kStages batches ago on this stream (a wait for the last one
+  // would wait for everything enqueued before it)
+  const int sk = bs->next;
+  bs->next = (bs->next + 1) % kStages;
+  if (bs->pending[sk]) {
+    e = hipEventSynchronize(bs->staged[sk]);
     if (e != hipSuccess) return fail_hip(e, "batch staging wait");
-    bs->pending = false;
+    bs->pending[sk] = false;
   }
   const int32_t n[2] = {(int32_t)light.size(), (int32_t)descs.size()};
-  char* stage = (char*)bs->h_stage;
+  char* stage = (char*)bs->h_stage[sk];
   std::memcpy(stage + 64, n, sizeof n);
   std::memcpy(stage + kDescOffset, light.data(), sizeof(BatchImage) * light.size());
   std::memcpy(stage + kDescOffset + kClassBytes, descs.data(), sizeof(BatchImage) * descs.size());
@@ -320,9 +330,9 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
                        sizeof(WindowImage) * (wins[0].size() + wins[1].size()),
                        hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return fail_hip(e, "batch descriptor upload");
-  e = hipEventRecord(bs->staged, stream);
+  e = hipEventRecord(bs->staged[sk], stream);
   if (e != hipSuccess) return fail_hip(e, "batch staging event");
-  bs->pending = true;
+  bs->pending[sk] = true;
   if (any_win) {
     const WindowImage* d_win = (const WindowImage*)(base + kWinOffset);
     for (int c = 1; c >= 0; --c) {  // 16-bit images first: the longer work

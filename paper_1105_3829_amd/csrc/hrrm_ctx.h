@@ -17,12 +17,14 @@ struct TunedEntry {
 
 // Per-stream state of batched launches: descriptor buffer, work counter and
 // the captured graph of the launch.
+constexpr int kStages = 4;  // pinned staging copies per stream, used in turn
 struct BatchStream {
   hipStream_t stream;
-  void* d_buf;        // work counters, image counts, light and heavy descriptor regions
-  void* h_stage;      // pinned staging copy of d_buf's upload
-  hipEvent_t staged;  // recorded after the upload; the staging copy is reused after it
-  bool pending;
+  void* d_buf;                 // work counters, image counts, descriptor regions
+  void* h_stage[kStages];      // pinned staging copies of d_buf's upload
+  hipEvent_t staged[kStages];  // recorded after each upload; its copy is reused after it
+  bool pending[kStages];
+  int next;                    // staging copy of the next batch
   hipGraph_t graph;
   hipGraphExec_t exec;
 };
