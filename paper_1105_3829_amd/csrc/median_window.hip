@@ -57,6 +57,7 @@ constexpr int kPitch = 36;  // dwords per column's counters (36 = 4 mod 32: the
                             // 128-bit reads of 8 consecutive lanes hit distinct banks)
 constexpr int kLohi = 32;   // dword of the base's lo/hi counts (after its 32 leaf dwords)
 constexpr int kSink = 33;   // pad dword that takes the zero updates of values outside the leaves
+constexpr int kSpare = 34;  // pad dwords 34, 35 of columns 0..15: row16's 16-bit counts
 constexpr int kMaxPasses = 6;  // passes over one row before it is left to the tiered kernel
 
 // Where a value goes: leaf dword q with byte increment inc (values outside
@@ -87,8 +88,9 @@ __device__ __forceinline__ uint32_t dsum(uint32_t v, uint32_t acc) {
 }
 
 // One wave's LDS: bins[ncols][kPitch], lohi[ncols], base[kPitch] (the leaf
-// counts of the window of the wave's first pixel; base[kLohi] its lo/hi), then
-// 32 dwords for row16, 16-byte aligned.
+// counts of the window of the wave's first pixel; base[kLohi] its lo/hi),
+// 16-byte aligned.  (LDS is granted in blocks of 1,280 bytes: at r = 15 these
+// 14,064 bytes take 11 blocks, so 11 one-wave workgroups share a CU.)
 struct WaveLds {
   uint32_t* bins;
   uint32_t* lohi;
@@ -422,17 +424,17 @@ __device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane
 // in one window: clamp-to-edge repeats a corner pixel (r+1)^2 times).
 // `below` is each pixel's exact window count below these leaves.  Per lane:
 // ok = its order statistic lies in these leaves, off its leaf offset, cnt the
-// exact number of window values in these leaves.  b16: 32 dwords of the
-// wave's LDS for the 16-bit counts of the wave's first window.  All 64 lanes
-// active.
-__device__ __forceinline__ void row16(const WaveLds& L, uint32_t* b16, int qs, int lane, int r2,
-                                      int rank, int below, int& off, bool& ok, int& cnt) {
+// exact number of window values in these leaves.  The 16-bit counts of the
+// wave's first window go to the pad dwords kSpare, kSpare + 1 of columns
+// 0..15 (pair q in column q).  All 64 lanes active.
+__device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2, int rank,
+                                      int below, int& off, bool& ok, int& cnt) {
   // the first window's counts, summed again from its 2r + 1 columns
   if (lane < 32) {
     uint32_t acc = 0;
     const int q = qs + (lane >> 1), sh = (lane & 1) * 8;
     for (int c = 0; c <= r2; ++c) acc += (L.bins[c * kPitch + q] >> sh) & 0x00ff00ffu;
-    b16[lane] = acc;
+    L.bins[(lane >> 1) * kPitch + kSpare + (lane & 1)] = acc;
   }
   __builtin_amdgcn_wave_barrier();
   const int ci = lane + r2;
@@ -449,9 +451,10 @@ __device__ __forceinline__ void row16(const WaveLds& L, uint32_t* b16, int qs, i
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int q = k + i;
-      F[2 * q] = b16[2 * q] + wave_scan((av[i] & 0x00ff00ffu) - (bv[i] & 0x00ff00ffu));
+      const uint2 b16 = *(const uint2*)(L.bins + q * kPitch + kSpare);
+      F[2 * q] = b16.x + wave_scan((av[i] & 0x00ff00ffu) - (bv[i] & 0x00ff00ffu));
       F[2 * q + 1] =
-          b16[2 * q + 1] + wave_scan(((av[i] >> 8) & 0x00ff00ffu) - ((bv[i] >> 8) & 0x00ff00ffu));
+          b16.y + wave_scan(((av[i] >> 8) & 0x00ff00ffu) - ((bv[i] >> 8) & 0x00ff00ffu));
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -631,7 +634,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         for (int qs = q0; qs < q0 + (!wide ? 16 : kBinQ); qs += 16) {
           int off16, cnt16;
           bool ok16;
-          row16(L, L.base + kPitch, qs, lane, r2, rank, below, off16, ok16, cnt16);
+          row16(L, qs, lane, r2, rank, below, off16, ok16, cnt16);
           if (!have && ok16) {
             res = bc + 4 * qs + off16;
             have = true;
@@ -870,7 +873,8 @@ int64_t window_tiles(const WindowArgs& a) {
 
 int window_waves_per_cu(int bytes, int r) {
   const int wpg = kc_for(r) <= 2 ? (bytes == 2 ? 1 : 4) : window_waves_per_group(r);
-  const size_t per = (size_t)wpg * window_wave_bytes(r);
+  // (LDS is granted to a workgroup in blocks of 1,280 bytes)
+  const size_t per = ((size_t)wpg * window_wave_bytes(r) + 1279) / 1280 * 1280;
   const int groups = (int)((size_t)kLdsLimit / per);
   const int waves = groups * wpg;
   return waves < 32 ? (waves > 0 ? waves : 1) : 32;
@@ -901,8 +905,8 @@ hipError_t launch_window_multi(const WindowImage* d_imgs, int n, int64_t groups,
 
 size_t window_wave_bytes(int r) {
   const int ncols = 64 + 2 * r;
-  // + base (kPitch dwords) + the 16-bit counts of the first window (32)
-  return window_base_offset(ncols) + (size_t)(kPitch + 32) * 4;
+  // + base (kPitch dwords)
+  return window_base_offset(ncols) + (size_t)kPitch * 4;
 }
 
 int window_waves_per_group(int r) {
