@@ -15,6 +15,7 @@
 #include "hrrm.h"
 #include "hrrm_ctx.h"
 #include "hrrm_internal.h"
+#include "window_geom.hpp"
 #include "host_logic.hpp"
 
 namespace hrrm {
@@ -353,46 +354,13 @@ int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, 
   wa.rank = rank;
   wa.r = r;
   wa.n = (2 * r + 1) * (2 * r + 1);
-  wa.strips = (int32_t)((w + 63) / 64);
-  int64_t seg = t.window_rows;
-  // waves the GPU holds at once
+  // waves the GPU holds at once (segment sizing of an image launched alone)
   const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(bytes, r);
-  if (alone && seg > 8 && (int64_t)wa.strips * ((h + seg - 1) / seg) < 2 * slots) {
-    // too few segments for two generations of waves: shorter ones (C1-like
-    // 1024^2 r = 15: 8-row segments finish about 3x sooner than 32-row ones)
-    seg = std::max<int64_t>(8, std::min<int64_t>(seg, (int64_t)wa.strips * h / (2 * slots)));
-  }
-  wa.seg_rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(seg, h));
-  wa.segs = (int32_t)((h + wa.seg_rows - 1) / wa.seg_rows);
-  wa.border_rows = std::max<int32_t>(1, std::min<int32_t>(wa.seg_rows, 8));
-  {
-    const int64_t br = wa.border_rows, inner = wa.strips > 2 ? wa.strips - 2 : 0;
-    const int64_t top_end = std::min<int64_t>(h, wa.seg_rows);
-    const int64_t bot_start = std::max<int64_t>(top_end, h - wa.seg_rows);
-    wa.top_end = (int32_t)top_end;
-    wa.bot_start = (int32_t)bot_start;
-    // the last generation of inner-strip segments at half height, so that
-    // the launch's last waves end together (u16 4096^2 r = 15: the 32-row
-    // segments' last generation started at 336 of 473 us; 0.48 -> 0.465 ms,
-    // r = 7 0.82 -> 0.77, r = 31 0.63 -> 0.60).  Past r = 32 a segment's
-    // build of 2r + 1 rows costs more than the shorter tail saves (r = 50
-    // 1.20 -> 1.27 ms).
-    wa.tail_rows = std::max<int32_t>(1, wa.seg_rows / 2);
-    int64_t tail_start = bot_start;
-    if (alone && inner > 0 && wa.seg_rows >= 16 && r <= 32) {
-      const int64_t tail_segs = (slots + inner - 1) / inner;
-      tail_start = std::max<int64_t>(top_end, bot_start - tail_segs * wa.tail_rows);
-    }
-    wa.tail_start = (int32_t)tail_start;
-    wa.side_tiles = (int32_t)((wa.strips > 1 ? 2 : 1) * ((h + br - 1) / br));
-    wa.top_tiles = (int32_t)(inner * ((top_end + br - 1) / br));
-    wa.border_tiles =
-        (int32_t)(wa.side_tiles + wa.top_tiles + inner * ((h - bot_start + br - 1) / br));
-  }
+  window_geometry(wa, w, h, t.window_rows, slots, alone, r);
   wa.wave_bytes = (int32_t)window_wave_bytes(r);
   wa.fb_strips = fa.strips;
   wa.fb_rows = fa.seg_rows;
-  if ((int64_t)wa.strips * (wa.segs + 4 * (h / wa.border_rows + 1)) > 0x7fffffffLL)
+  if (window_tile_count(wa) > 0x7fffffffLL)
     return fail(HRRM_EUNSUPPORTED, "image too large for one launch");
   return HRRM_OK;
 }

@@ -48,6 +48,7 @@
 // of its 2r + 1 columns).
 #include "hrrm_internal.h"
 #include "wave.hpp"
+#include "window_geom.hpp"
 
 namespace hrrm {
 namespace {
@@ -494,39 +495,8 @@ template <typename T, bool ADAPT, int KC>
 __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, int wv,
                                             uint8_t* lds) {
   const int lane = threadIdx.x & 63;
-  const int inner = a.strips > 2 ? a.strips - 2 : 0;
-  const int64_t mid_tiles =
-      inner ? (int64_t)inner * ((a.tail_start - a.top_end + a.seg_rows - 1) / a.seg_rows) : 0;
-  const int64_t tail_tiles =
-      inner ? (int64_t)inner * ((a.bot_start - a.tail_start + a.tail_rows - 1) / a.tail_rows) : 0;
-  if (tile >= (int64_t)a.border_tiles + mid_tiles + tail_tiles) return;
   int strip, y0, y1;
-  if (tile < a.side_tiles) {
-    const int sides = a.strips > 1 ? 2 : 1;
-    strip = (int)(tile % sides) ? a.strips - 1 : 0;
-    y0 = (int)(tile / sides) * a.border_rows;
-    y1 = y0 + a.border_rows;
-  } else if (tile < a.side_tiles + a.top_tiles) {
-    const int j = (int)(tile - a.side_tiles);
-    strip = 1 + j % inner;
-    y0 = (j / inner) * a.border_rows;
-    y1 = y0 + a.border_rows < a.top_end ? y0 + a.border_rows : a.top_end;
-  } else if (tile < a.border_tiles) {
-    const int j = (int)(tile - a.side_tiles - a.top_tiles);
-    strip = 1 + j % inner;
-    y0 = a.bot_start + (j / inner) * a.border_rows;
-    y1 = y0 + a.border_rows;
-  } else if (tile < a.border_tiles + mid_tiles) {
-    const int64_t j = tile - a.border_tiles;
-    strip = 1 + (int)(j % inner);
-    y0 = a.top_end + (int)(j / inner) * a.seg_rows;
-    y1 = y0 + a.seg_rows < a.tail_start ? y0 + a.seg_rows : a.tail_start;
-  } else {
-    const int64_t j = tile - a.border_tiles - mid_tiles;
-    strip = 1 + (int)(j % inner);
-    y0 = a.tail_start + (int)(j / inner) * a.tail_rows;
-    y1 = y0 + a.tail_rows < a.bot_start ? y0 + a.tail_rows : a.bot_start;
-  }
+  if (!window_tile_rows(a, tile, strip, y0, y1)) return;
   const T* __restrict__ src = (const T*)a.src;
   T* __restrict__ dst = (T*)a.dst;
   const int r = a.r, r2 = 2 * a.r, ncols = 64 + 2 * a.r;
@@ -864,12 +834,7 @@ hipError_t prime_w() {
 
 }  // namespace
 
-int64_t window_tiles(const WindowArgs& a) {
-  const int64_t inner = a.strips > 2 ? a.strips - 2 : 0;
-  if (!inner) return a.border_tiles;
-  return (int64_t)a.border_tiles + inner * ((a.tail_start - a.top_end + a.seg_rows - 1) / a.seg_rows) +
-         inner * ((a.bot_start - a.tail_start + a.tail_rows - 1) / a.tail_rows);
-}
+int64_t window_tiles(const WindowArgs& a) { return window_tile_count(a); }
 
 int window_waves_per_cu(int bytes, int r) {
   const int wpg = kc_for(r) <= 2 ? (bytes == 2 ? 1 : 4) : window_waves_per_group(r);
