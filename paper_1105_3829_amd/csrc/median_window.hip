@@ -56,7 +56,7 @@ namespace {
 constexpr int kBinQ = 32;   // dwords of byte counters per column: 128 grey levels
 constexpr int kPitch = 36;  // dwords per column's counters (36 = 4 mod 32: the
                             // 128-bit reads of 8 consecutive lanes hit distinct banks)
-constexpr int kLohi = 32;   // dword of the base's lo/hi counts (after its 32 leaf dwords)
+constexpr int kLohi = 32;   // dword of the lo/hi counts of a column (and of the base)
 constexpr int kSink = 33;   // pad dword that takes the zero updates of values outside the leaves
 constexpr int kSpare = 34;  // pad dwords 34, 35 of columns 0..15: row16's 16-bit counts
 constexpr int kMaxPasses = 6;  // passes over one row before it is left to the tiered kernel
@@ -88,18 +88,23 @@ __device__ __forceinline__ uint32_t dsum(uint32_t v, uint32_t acc) {
   return __builtin_amdgcn_sad_u8(v, 0u, acc);  // acc + sum of the four bytes
 }
 
-// One wave's LDS: bins[ncols][kPitch], lohi[ncols], base[kPitch] (the leaf
-// counts of the window of the wave's first pixel; base[kLohi] its lo/hi),
-// 16-byte aligned.  (LDS is granted in blocks of 1,280 bytes: at r = 15 these
-// 14,064 bytes take 11 blocks, so 11 one-wave workgroups share a CU.)
+// One wave's LDS: bins[ncols][kPitch] (a column's lo/hi counts in its dword
+// kLohi), base[kPitch] (the leaf counts of the window of the wave's first
+// pixel; base[kLohi] its lo/hi).  (LDS is granted in blocks of 1,280 bytes:
+// at r = 15 these 13,680 bytes take 11 blocks, so 11 one-wave workgroups
+// share a CU; at r = 7, 11,376 bytes take 9: 14 waves.)
 struct WaveLds {
   uint32_t* bins;
-  uint32_t* lohi;
   uint32_t* base;
 };
 
 __host__ __device__ constexpr size_t window_base_offset(int ncols) {
-  return (((size_t)ncols * (kPitch + 1) * 4 + 15) & ~(size_t)15);
+  return (size_t)ncols * kPitch * 4;
+}
+
+// The lo/hi word of column c.
+__device__ __forceinline__ uint32_t* lohi_of(const WaveLds& L, int c) {
+  return L.bins + c * kPitch + kLohi;
 }
 
 template <int N>
@@ -181,7 +186,7 @@ __device__ __forceinline__ vu<SQ> window_counts(const WaveLds& L, int q0, int la
     W[k + 2] = c.z + wave_scan(a.z - b.z);
     W[k + 3] = c.w + wave_scan(a.w - b.w);
   }
-  wl = L.base[kLohi] + wave_scan(L.lohi[ci] - L.lohi[co]);
+  wl = L.base[kLohi] + wave_scan(*lohi_of(L, ci) - *lohi_of(L, co));
   return W;
 }
 
@@ -335,7 +340,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k)
-    if (lane + 64 * k < ncols) L.lohi[lane + 64 * k] = lohi[k];
+    if (lane + 64 * k < ncols) *lohi_of(L, lane + 64 * k) = lohi[k];
   __builtin_amdgcn_wave_barrier();
   if (lane <= kBinQ) {
     uint32_t s = 0;
@@ -344,7 +349,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
       for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * kPitch + lane];
     } else {
 #pragma unroll 8
-      for (int c = 0; c <= 2 * r; ++c) s += L.lohi[c];
+      for (int c = 0; c <= 2 * r; ++c) s += *lohi_of(L, c);
     }
     L.base[lane] = s;  // lane kBinQ writes base[kLohi]
   }
@@ -380,7 +385,7 @@ __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, in
       const uint32_t dlo = q1 > q0 ? lo : 0u - lo;
       const uint32_t dhi = e1 > e0 ? 0u - hi : hi;
       const uint32_t d = dlo + (dhi << 16);
-      if (d) lds_add(L.lohi + c, d);
+      if (d) lds_add(lohi_of(L, c), d);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -388,7 +393,7 @@ __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, in
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int c = lane + 64 * k;
-    if (c <= r2) s += L.lohi[c];
+    if (c <= r2) s += *lohi_of(L, c);
   }
   s = wave_scan(s);
   if (lane == 63) L.base[kLohi] = s;
@@ -511,7 +516,6 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
 
   WaveLds L;
   L.bins = (uint32_t*)(lds + (size_t)wv * a.wave_bytes);
-  L.lohi = L.bins + (size_t)ncols * kPitch;
   L.base = (uint32_t*)(lds + (size_t)wv * a.wave_bytes + window_base_offset(ncols));
   const int wave_dwords = a.wave_bytes / 4;
 
@@ -743,7 +747,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         uint32_t* col = L.bins + c * kPitch;
         lds_add(col + i.q, di);
         lds_add(col + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
-        lds_add(L.lohi + c, dl);
+        lds_add(lohi_of(L, c), dl);
         if (c <= r2) {
           lds_add(L.base + i.q, di);
           lds_add(L.base + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
