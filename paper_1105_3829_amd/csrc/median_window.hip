@@ -90,9 +90,10 @@ __device__ __forceinline__ uint32_t dsum(uint32_t v, uint32_t acc) {
 
 // One wave's LDS: bins[ncols][kPitch] (a column's lo/hi counts in its dword
 // kLohi), base[kPitch] (the leaf counts of the window of the wave's first
-// pixel; base[kLohi] its lo/hi).  (LDS is granted in blocks of 1,280 bytes:
-// at r = 15 these 13,680 bytes take 11 blocks, so 11 one-wave workgroups
-// share a CU; at r = 7, 11,376 bytes take 9: 14 waves.)
+// pixel; base[kLohi] its lo/hi), then kPitch dwords that stay zero.  (LDS is
+// granted in blocks of 1,280 bytes: at r = 15 these 13,824 bytes take 11
+// blocks, so 11 one-wave workgroups share a CU; at r = 7, 11,520 bytes take
+// 9: 14 waves.)
 struct WaveLds {
   uint32_t* bins;
   uint32_t* base;
@@ -166,27 +167,28 @@ __device__ __forceinline__ bool step(uint32_t c, uint32_t& k) {
 }
 
 // Window counts of the scanned range for every lane's pixel: W[k] = leaf
-// bytes of dword q0 + k, wl = lo | hi << 16.  All 64 lanes active.
+// bytes of dword q0 + k, wl = lo | hi << 16.  Lane x >= 1 contributes the
+// difference of the columns entering and leaving its window; lane 0 the base
+// (block ncols) minus the zero block (block ncols + 1), so that the prefix sum
+// over the wave is the window counts themselves.  All 64 lanes active.
 template <int SQ>
 __device__ __forceinline__ vu<SQ> window_counts(const WaveLds& L, int q0, int lane, int r2,
-                                                uint32_t& wl) {
-  const int ci = lane + r2;                  // column x + r
-  const int co = lane == 0 ? ci : lane - 1;  // column x - r - 1 (lane 0: none)
+                                                int ncols, uint32_t& wl) {
+  const int ci = lane ? lane + r2 : ncols;      // column x + r
+  const int co = lane ? lane - 1 : ncols + 1;   // column x - r - 1
   const uint32_t* pi = L.bins + ci * kPitch + q0;
   const uint32_t* po = L.bins + co * kPitch + q0;
-  const uint32_t* pb = L.base + q0;
   vu<SQ> W;
 #pragma unroll
   for (int k = 0; k < SQ; k += 4) {
     const uint4 a = *(const uint4*)(pi + k);
     const uint4 b = *(const uint4*)(po + k);
-    const uint4 c = *(const uint4*)(pb + k);
-    W[k] = c.x + wave_scan(a.x - b.x);
-    W[k + 1] = c.y + wave_scan(a.y - b.y);
-    W[k + 2] = c.z + wave_scan(a.z - b.z);
-    W[k + 3] = c.w + wave_scan(a.w - b.w);
+    W[k] = wave_scan(a.x - b.x);
+    W[k + 1] = wave_scan(a.y - b.y);
+    W[k + 2] = wave_scan(a.z - b.z);
+    W[k + 3] = wave_scan(a.w - b.w);
   }
-  wl = L.base[kLohi] + wave_scan(*lohi_of(L, ci) - *lohi_of(L, co));
+  wl = wave_scan(*lohi_of(L, ci) - *lohi_of(L, co));
   return W;
 }
 
@@ -410,10 +412,10 @@ struct RowOut {
 };
 
 template <int SQ>
-__device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane, int r2, int n,
+__device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane, int r2, int ncols, int n,
                                               int rank, bool live) {
   uint32_t wl;
-  const vu<SQ> W = window_counts<SQ>(L, q0, lane, r2, wl);
+  const vu<SQ> W = window_counts<SQ>(L, q0, lane, r2, ncols, wl);
   const int lo = (int)(wl & 0xffffu), hi = (int)(wl >> 16);
   const int win = n - lo - hi;
   const int kp = rank - lo;
@@ -592,9 +594,9 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     for (int tries = 0;; ++tries) {
       RowOut o;
       if (!wide)
-        o = row_medians<16>(L, q0, lane, r2, a.n, rank, live);
+        o = row_medians<16>(L, q0, lane, r2, ncols, a.n, rank, live);
       else
-        o = row_medians<kBinQ>(L, q0, lane, r2, a.n, rank, live);
+        o = row_medians<kBinQ>(L, q0, lane, r2, ncols, a.n, rank, live);
       if (!have && o.ok) {
         res = bc + 4 * q0 + o.off;
         have = true;
@@ -874,8 +876,8 @@ hipError_t launch_window_multi(const WindowImage* d_imgs, int n, int64_t groups,
 
 size_t window_wave_bytes(int r) {
   const int ncols = 64 + 2 * r;
-  // + base (kPitch dwords)
-  return window_base_offset(ncols) + (size_t)kPitch * 4;
+  // + base and a block of zeros (kPitch dwords each)
+  return window_base_offset(ncols) + (size_t)2 * kPitch * 4;
 }
 
 int window_waves_per_group(int r) {
