@@ -135,7 +135,9 @@ struct WindowImage {
 };
 
 size_t window_wave_bytes(int r);
-// Waves of one window launch (element size `bytes`, radius r) that fit a CU.
+// Waves per workgroup of a single window launch (element size `bytes`,
+// radius r), and the waves of that launch that fit a CU.
+int window_launch_wpg(int bytes, int r);
 int window_waves_per_cu(int bytes, int r);
 int64_t window_tiles(const WindowArgs& a);
 // Waves per workgroup of a multi-image window launch of `bytes`-byte images

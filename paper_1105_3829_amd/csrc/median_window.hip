@@ -811,16 +811,12 @@ hipError_t launch_k(const WindowArgs& a, hipStream_t stream) {
 template <typename T, bool ADAPT>
 hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
   const int kc = kc_for(a.r);
-  const int wpg = window_waves_per_group(a.r);
-  // r <= 32: one-wave workgroups let 11 waves share a CU (16-bit X-ray-like
-  // 4096^2 r = 15: 0.47 -> 0.41 ms); four-wave workgroups suit the 8-bit
-  // launches, which have four times the waves (8-bit low-key 8192^2 r = 8:
-  // 0.94 -> 0.87 ms)
+  const int wpg = window_launch_wpg((int)sizeof(T), a.r);
   if (kc <= 2)
-    return sizeof(T) == 2 ? launch_k<T, ADAPT, 2, 1>(a, stream) : launch_k<T, ADAPT, 2, 4>(a, stream);
-  if (kc == 3) return wpg >= 4 ? launch_k<T, ADAPT, 3, 4>(a, stream)
+    return wpg == 4 ? launch_k<T, ADAPT, 2, 4>(a, stream) : launch_k<T, ADAPT, 2, 1>(a, stream);
+  if (kc == 3) return wpg == 4 ? launch_k<T, ADAPT, 3, 4>(a, stream)
                                : launch_k<T, ADAPT, 3, 2>(a, stream);
-  return wpg >= 2 ? launch_k<T, ADAPT, 5, 2>(a, stream) : launch_k<T, ADAPT, 5, 1>(a, stream);
+  return wpg == 2 ? launch_k<T, ADAPT, 5, 2>(a, stream) : launch_k<T, ADAPT, 5, 1>(a, stream);
 }
 
 template <typename T, bool ADAPT>
@@ -842,14 +838,30 @@ hipError_t prime_w() {
 
 int64_t window_tiles(const WindowArgs& a) { return window_tile_count(a); }
 
-int window_waves_per_cu(int bytes, int r) {
-  const int wpg = kc_for(r) <= 2 ? (bytes == 2 ? 1 : 4) : window_waves_per_group(r);
-  // (LDS is granted to a workgroup in blocks of 1,280 bytes)
+// Waves per CU with workgroups of wpg waves at radius r (LDS is granted to a
+// workgroup in blocks of 1,280 bytes).
+static int waves_at(int wpg, int r) {
   const size_t per = ((size_t)wpg * window_wave_bytes(r) + 1279) / 1280 * 1280;
-  const int groups = (int)((size_t)kLdsLimit / per);
-  const int waves = groups * wpg;
+  const int waves = (int)((size_t)kLdsLimit / per) * wpg;
   return waves < 32 ? (waves > 0 ? waves : 1) : 32;
 }
+
+int window_launch_wpg(int bytes, int r) {
+  const int kc = kc_for(r);
+  if (kc <= 2) {
+    // one- or four-wave workgroups, whichever lets more waves share a CU
+    // (16-bit X-ray-like 4096^2 r = 15: 11 against 8 waves, 0.47 -> 0.41 ms);
+    // on a tie 8-bit launches, which have four times the waves, take four
+    // (8-bit low-key 8192^2 r = 8: 0.94 -> 0.87 ms)
+    const int w1 = waves_at(1, r), w4 = waves_at(4, r);
+    return bytes == 1 ? (w4 >= w1 ? 4 : 1) : (w1 >= w4 ? 1 : 4);
+  }
+  const int wpg = window_waves_per_group(r);
+  if (kc == 3) return wpg >= 4 ? 4 : 2;
+  return wpg >= 2 ? 2 : 1;
+}
+
+int window_waves_per_cu(int bytes, int r) { return waves_at(window_launch_wpg(bytes, r), r); }
 
 int window_multi_waves(int bytes, int r_max) {
   return kc_for(r_max) > 2 ? 0 : bytes == 2 ? 1 : 4;
