@@ -121,9 +121,13 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
       continue;  // (rejected below)
     const int bytes = im.dtype == HRRM_U8 ? 1 : 2;
     const TileConfig t = ctx->tile_for(bytes, 2, im.r, false, im.width, im.height, 1, false);
+    if (t.window_rows > 0 && window_bq(bytes, im.r, false) != 32) {
+      solo[i] = 1;  // (the multi-image launch holds 128 grey levels per column)
+      continue;
+    }
     if (t.window_rows > 0 && window_multi_waves(bytes, im.r) > 0) {
       const int64_t own = (im.width + 63) / 64 * ((im.height + t.window_rows - 1) / t.window_rows);
-      if (own >= cus * window_waves_per_cu(bytes, im.r)) {
+      if (own >= cus * window_waves_per_cu(bytes, im.r, 32)) {
         solo[i] = 1;
         continue;
       }
@@ -152,7 +156,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
   const int64_t tier_seg = std::max<int64_t>(8, tier_rows / (4 * (int64_t)ctx->cu_count()));
   int64_t win_seg[2];
   for (int c = 0; c < 2; ++c) {
-    const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(c + 1, win_r[c]);
+    const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(c + 1, win_r[c], 32);
     win_seg[c] = std::max<int64_t>(8, win_rows[c] / (2 * slots));
   }
   for (int i = 0; i < count; ++i) {
@@ -174,7 +178,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
       MedianArgs fa;
       const int64_t n = (int64_t)(2 * im.r + 1) * (2 * im.r + 1);
       int rc = window_setup(ctx, t, im.src, im.dst, bytes, im.width, im.height, im.src_row_stride,
-                            im.dst_row_stride, im.r, (n - 1) / 2, wi.args, fa, false);
+                            im.dst_row_stride, im.r, (n - 1) / 2, false, wi.args, fa, false);
       if (rc != HRRM_OK) return fail(rc, "image %d: %s", i, hrrm_last_error());
       // the flag offset for now; the pointer once the flag buffer is known
       wi.args.need = nullptr;

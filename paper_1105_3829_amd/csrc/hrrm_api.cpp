@@ -187,13 +187,15 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   //   against 1.61);
   //   8-bit adaptive r = 1..32 (low-key r = 1 0.80, r = 32 3.5 against the
   //   topology-tree's 6.4 ms; r = 64 9.9 against 7.8);
-  //   16-bit uniform tree from r = 6 (X-ray-like 4096^2 r = 6 1.28 against
-  //   1.56 ms, r = 15 0.49 against 1.41; at r <= 5 the medians of
-  //   neighbouring pixels spread wider than the grey-level window), and
-  //   16-bit adaptive at every r (r = 5 1.88 against 11 ms)
+  //   16-bit uniform tree from r = 4 (X-ray-like 4096^2, 256 grey levels
+  //   per column up to r = 7: r = 4 0.93 against 1.44 ms, r = 5 0.69
+  //   against 1.79, r = 7 0.59 against 1.38; 128 from r = 8: r = 15 0.42
+  //   against 1.41; at r <= 3 a row's medians spread over more than 256
+  //   grey levels: r = 3 2.05 against 1.07), and 16-bit adaptive at every r
+  //   (r = 5 1.88 against 11 ms)
   t.window_rows = 0;
   if (dims == 2 && r >= 1 &&
-      (bytes == 1 ? r <= (adaptive ? 32 : 24) : (adaptive || r >= 6)))
+      (bytes == 1 ? r <= (adaptive ? 32 : 24) : (adaptive || r >= 4)))
     t.window_rows = r <= 24 ? 32 : 64;  // C1 r = 15: 0.41 adaptive, 0.49 ms plain
   // an image filtered on its own keeps at least two tiles per workgroup slot
   // of the GPU (256 CUs, 1 to 6 workgroups each) when it allows it; in a
@@ -334,7 +336,7 @@ static int tiered_args(const TileConfig& t0, int bytes, int dims, bool adaptive,
 // tiles the window kernel flags; neither `need` pointer is set.
 int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
                  int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
-                 WindowArgs& wa, MedianArgs& fa, bool alone) {
+                 bool adaptive, WindowArgs& wa, MedianArgs& fa, bool alone) {
   // rows the window kernel cannot finish are rare and come alone: short
   // fallback tiles
   TileConfig ft = ctx->tile_for(bytes, 2, r, false, w, h, 1);
@@ -355,9 +357,10 @@ int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, 
   wa.r = r;
   wa.n = (2 * r + 1) * (2 * r + 1);
   // waves the GPU holds at once (segment sizing of an image launched alone)
-  const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(bytes, r);
+  wa.bq = window_bq(bytes, r, adaptive);
+  const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(bytes, r, wa.bq);
   window_geometry(wa, w, h, t.window_rows, slots, alone, r);
-  wa.wave_bytes = (int32_t)window_wave_bytes(r);
+  wa.wave_bytes = (int32_t)window_wave_bytes(r, wa.bq);
   wa.fb_strips = fa.strips;
   wa.fb_rows = fa.seg_rows;
   if (window_tile_count(wa) > 0x7fffffffLL)
@@ -372,7 +375,7 @@ static int run_window(Context* ctx, const TileConfig& t, const void* src, void* 
                       bool adaptive, hipStream_t stream, uint32_t* need_buf) {
   WindowArgs wa;
   MedianArgs fa;
-  int rc = window_setup(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, wa, fa, true);
+  int rc = window_setup(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, adaptive, wa, fa, true);
   if (rc != HRRM_OK) return rc;
   const int64_t tiles = (int64_t)fa.strips * fa.segs;
   hipError_t e = hipSetDevice(ctx->device);

@@ -85,7 +85,7 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
 // segments); in a batch the other images fill it
 int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
                  int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
-                 WindowArgs& wa, MedianArgs& fa, bool alone);
+                 bool adaptive, WindowArgs& wa, MedianArgs& fa, bool alone);
 // est / est_rs: optional estimate image for the adaptive topology (2-D)
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
                int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,

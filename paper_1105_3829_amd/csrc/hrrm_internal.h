@@ -123,6 +123,7 @@ struct WindowArgs {
   int32_t border_rows, border_tiles, side_tiles, top_tiles, top_end, bot_start;
   int32_t tail_start, tail_rows;
   int32_t wave_bytes;  // LDS bytes of one wave
+  int32_t bq;          // dwords of leaf counters per column: 32 or 64 (uniform tree)
   uint32_t* need;
   int32_t fb_strips, fb_rows;
 };
@@ -134,11 +135,15 @@ struct WindowImage {
   int64_t group_end;
 };
 
-size_t window_wave_bytes(int r);
+// LDS bytes of one wave of a window launch at radius r with bq dwords of leaf
+// counters per column (32: 128 grey levels, 64: 256).
+size_t window_wave_bytes(int r, int bq);
+// Leaf dwords per column of a window launch (element size `bytes`, radius r).
+int window_bq(int bytes, int r, bool adaptive);
 // Waves per workgroup of a single window launch (element size `bytes`,
 // radius r), and the waves of that launch that fit a CU.
-int window_launch_wpg(int bytes, int r);
-int window_waves_per_cu(int bytes, int r);
+int window_launch_wpg(int bytes, int r, int bq);
+int window_waves_per_cu(int bytes, int r, int bq);
 int64_t window_tiles(const WindowArgs& a);
 // Waves per workgroup of a multi-image window launch of `bytes`-byte images
 // whose largest radius is r_max; 0 when no such launch exists (r_max > 32).

@@ -53,12 +53,16 @@
 namespace hrrm {
 namespace {
 
-constexpr int kBinQ = 32;   // dwords of byte counters per column: 128 grey levels
-constexpr int kPitch = 36;  // dwords per column's counters (36 = 4 mod 32: the
-                            // 128-bit reads of 8 consecutive lanes hit distinct banks)
-constexpr int kLohi = 32;   // dword of the lo/hi counts of a column (and of the base)
-constexpr int kSink = 33;   // pad dword that takes the zero updates of values outside the leaves
-constexpr int kSpare = 34;  // pad dwords 34, 35 of columns 0..15: row16's 16-bit counts
+// Layout of a column's counters, for BQ dwords of byte counters (4 BQ grey
+// levels: 128 or 256), written out in each function as
+//   kBinQ = BQ          dwords of byte counters per column
+//   kPitch = BQ + 4     dwords per column (= 4 mod 32: the 128-bit reads of 8
+//                       consecutive lanes hit distinct banks)
+//   kLohi = BQ          dword of the lo/hi counts of a column (and of the base)
+//   kSink = BQ + 1      pad dword that takes the zero updates of values outside
+//                       the leaves
+//   kSpare = BQ + 2     pad dwords BQ + 2, BQ + 3 of columns 0..15: row16's
+//                       16-bit counts
 constexpr int kMaxPasses = 6;  // passes over one row before it is left to the tiered kernel
 
 // Where a value goes: leaf dword q with byte increment inc (values outside
@@ -69,7 +73,10 @@ struct Cls {
   uint32_t inc, lh;
 };
 
+template <int BQ>
 __device__ __forceinline__ Cls classify(int v, int bc, int q0, int sq) {
+  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
+  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
   const int rel = v - bc;
   const bool in = (uint32_t)rel < 4u * kBinQ;
   Cls c;
@@ -99,13 +106,14 @@ struct WaveLds {
   uint32_t* base;
 };
 
-__host__ __device__ constexpr size_t window_base_offset(int ncols) {
-  return (size_t)ncols * kPitch * 4;
+__host__ __device__ constexpr size_t window_base_offset(int ncols, int bq) {
+  return (size_t)ncols * (bq + 4) * 4;
 }
 
 // The lo/hi word of column c.
+template <int BQ>
 __device__ __forceinline__ uint32_t* lohi_of(const WaveLds& L, int c) {
-  return L.bins + c * kPitch + kLohi;
+  return L.bins + c * (BQ + 4) + BQ;
 }
 
 template <int N>
@@ -171,9 +179,11 @@ __device__ __forceinline__ bool step(uint32_t c, uint32_t& k) {
 // difference of the columns entering and leaving its window; lane 0 the base
 // (block ncols) minus the zero block (block ncols + 1), so that the prefix sum
 // over the wave is the window counts themselves.  All 64 lanes active.
-template <int SQ>
+template <int BQ, int SQ>
 __device__ __forceinline__ vu<SQ> window_counts(const WaveLds& L, int q0, int lane, int r2,
                                                 int ncols, uint32_t& wl) {
+  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
+  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
   const int ci = lane ? lane + r2 : ncols;      // column x + r
   const int co = lane ? lane - 1 : ncols + 1;   // column x - r - 1
   const uint32_t* pi = L.bins + ci * kPitch + q0;
@@ -188,7 +198,7 @@ __device__ __forceinline__ vu<SQ> window_counts(const WaveLds& L, int q0, int la
     W[k + 2] = wave_scan(a.z - b.z);
     W[k + 3] = wave_scan(a.w - b.w);
   }
-  wl = wave_scan(*lohi_of(L, ci) - *lohi_of(L, co));
+  wl = wave_scan(*lohi_of<BQ>(L, ci) - *lohi_of<BQ>(L, co));
   return W;
 }
 
@@ -220,6 +230,19 @@ __device__ __forceinline__ int descend(vu<SQ> W, int kp, int win, bool& ok) {
     const bool b5 = step((d & 0xffu) + ((d >> 8) & 0xffu), k);
     const bool b6 = step((d >> (b5 ? 16 : 0)) & 0xffu, k);
     off = (b1 ? 32 : 0) + (b2 ? 16 : 0) + (b3 ? 8 : 0) + (b4 ? 4 : 0) + (b5 ? 2 : 0) + (b6 ? 1 : 0);
+  } else if constexpr (SQ == 64) {
+    const vu<4> t4 = pairs<8>(t3);
+    const bool bh = step(t4[0] + t4[1], k);
+    const bool b0 = step(pick<2>(evens<4>(t4), bh), k);
+    const bool b1 = step(pick<4>(evens<8>(t3), bh, b0), k);
+    const bool b2 = step(pick<8>(evens<16>(t2), bh, b0, b1), k);
+    const bool b3 = step(pick<16>(evens<32>(t1), bh, b0, b1, b2), k);
+    const bool b4 = step(pick<32>(evens<64>(t0), bh, b0, b1, b2, b3), k);
+    const uint32_t d = pick<64>(W, bh, b0, b1, b2, b3, b4);
+    const bool b5 = step((d & 0xffu) + ((d >> 8) & 0xffu), k);
+    const bool b6 = step((d >> (b5 ? 16 : 0)) & 0xffu, k);
+    off = (bh ? 128 : 0) + (b0 ? 64 : 0) + (b1 ? 32 : 0) + (b2 ? 16 : 0) + (b3 ? 8 : 0) +
+          (b4 ? 4 : 0) + (b5 ? 2 : 0) + (b6 ? 1 : 0);
   } else {
     const bool b0 = step(t3[0] + t3[1], k);
     const bool b1 = step(pick<2>(evens<4>(t3), b0), k);
@@ -303,11 +326,13 @@ __device__ __forceinline__ int window_rank_exact(const T* __restrict__ src, int6
 // y from the raw values: zero, insert the 2r + 1 clamped rows of each column,
 // then base = sum of columns 0..2r.  Values are loaded sixteen rows at a time
 // before any is inserted, so their latencies overlap.
-template <typename T, int KC>
+template <typename T, int KC, int BQ>
 __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, int h, int r,
                                         const int (&gx)[KC], int ncols, const WaveLds& L,
                                         int wave_dwords, int y, int bc, int q0, int sq,
                                         int lane) {
+  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
+  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
   uint4* z = (uint4*)L.bins;
   for (int i = lane; i < wave_dwords / 4; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
   __builtin_amdgcn_wave_barrier();
@@ -332,7 +357,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
 #pragma unroll
         for (int t = 0; t < kBatch; ++t) {
           if (j0 + t <= r) {
-            const Cls cl = classify(v[t], bc, q0, sq);
+            const Cls cl = classify<BQ>(v[t], bc, q0, sq);
             lds_add(L.bins + c * kPitch + cl.q, cl.inc);
             lohi[k] += cl.lh;
           }
@@ -342,18 +367,19 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k)
-    if (lane + 64 * k < ncols) *lohi_of(L, lane + 64 * k) = lohi[k];
+    if (lane + 64 * k < ncols) *lohi_of<BQ>(L, lane + 64 * k) = lohi[k];
   __builtin_amdgcn_wave_barrier();
-  if (lane <= kBinQ) {
+  // base dword i (leaf dwords, then lo/hi at kLohi = kBinQ) by lane i % 64
+  for (int i = lane; i <= kBinQ; i += 64) {
     uint32_t s = 0;
-    if (lane < kBinQ) {
+    if (i < kBinQ) {
 #pragma unroll 8
-      for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * kPitch + lane];
+      for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * kPitch + i];
     } else {
 #pragma unroll 8
-      for (int c = 0; c <= 2 * r; ++c) s += *lohi_of(L, c);
+      for (int c = 0; c <= 2 * r; ++c) s += *lohi_of<BQ>(L, c);
     }
-    L.base[lane] = s;  // lane kBinQ writes base[kLohi]
+    L.base[i] = s;
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -364,9 +390,11 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
 // column leaf bytes are exact (at most 2r + 1 <= 255 values), so their digit
 // sums are the counts.  Then the base's lo/hi is summed again from the
 // columns.  All 64 lanes active.
-template <int KC>
+template <int KC, int BQ>
 __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, int q0, int s0,
                                          int q1, int s1, int lane) {
+  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
+  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
   const int la = q0 < q1 ? q0 : q1, lb = q0 < q1 ? q1 : q0;
   const int e0 = q0 + s0, e1 = q1 + s1;
   const int ha = e0 < e1 ? e0 : e1, hb = e0 < e1 ? e1 : e0;
@@ -387,7 +415,7 @@ __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, in
       const uint32_t dlo = q1 > q0 ? lo : 0u - lo;
       const uint32_t dhi = e1 > e0 ? 0u - hi : hi;
       const uint32_t d = dlo + (dhi << 16);
-      if (d) lds_add(lohi_of(L, c), d);
+      if (d) lds_add(lohi_of<BQ>(L, c), d);
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -395,7 +423,7 @@ __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, in
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
     const int c = lane + 64 * k;
-    if (c <= r2) s += *lohi_of(L, c);
+    if (c <= r2) s += *lohi_of<BQ>(L, c);
   }
   s = wave_scan(s);
   if (lane == 63) L.base[kLohi] = s;
@@ -411,11 +439,11 @@ struct RowOut {
   uint64_t low, high;
 };
 
-template <int SQ>
-__device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane, int r2, int ncols, int n,
-                                              int rank, bool live) {
+template <int BQ, int SQ>
+__device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane, int r2,
+                                              int ncols, int n, int rank, bool live) {
   uint32_t wl;
-  const vu<SQ> W = window_counts<SQ>(L, q0, lane, r2, ncols, wl);
+  const vu<SQ> W = window_counts<BQ, SQ>(L, q0, lane, r2, ncols, wl);
   const int lo = (int)(wl & 0xffffu), hi = (int)(wl >> 16);
   const int win = n - lo - hi;
   const int kp = rank - lo;
@@ -435,8 +463,11 @@ __device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane
 // exact number of window values in these leaves.  The 16-bit counts of the
 // wave's first window go to the pad dwords kSpare, kSpare + 1 of columns
 // 0..15 (pair q in column q).  All 64 lanes active.
+template <int BQ>
 __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2, int rank,
                                       int below, int& off, bool& ok, int& cnt) {
+  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
+  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
   // the first window's counts, summed again from its 2r + 1 columns
   if (lane < 32) {
     uint32_t acc = 0;
@@ -498,9 +529,11 @@ __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2
 // segments near the image's edges first (see WindowArgs), then the inner
 // strips' segments, neighbouring strips together); wv = the wave's index in
 // its workgroup, uniform (its LDS area).
-template <typename T, bool ADAPT, int KC>
+template <typename T, bool ADAPT, int KC, int BQ>
 __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, int wv,
                                             uint8_t* lds) {
+  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
+  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
   const int lane = threadIdx.x & 63;
   int strip, y0, y1;
   if (!window_tile_rows(a, tile, strip, y0, y1)) return;
@@ -518,7 +551,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
 
   WaveLds L;
   L.bins = (uint32_t*)(lds + (size_t)wv * a.wave_bytes);
-  L.base = (uint32_t*)(lds + (size_t)wv * a.wave_bytes + window_base_offset(ncols));
+  L.base = (uint32_t*)(lds + (size_t)wv * a.wave_bytes + window_base_offset(ncols, BQ));
   const int wave_dwords = a.wave_bytes / 4;
 
   y1 = y1 < h ? y1 : h;
@@ -533,12 +566,12 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   // lie well inside it until a median leaves it.  (16-bit: the medians of a
   // row at r = 10..31 rarely fit one subtree, and the second code path alone
   // measured 8 % slower; 8-bit low-key 8192^2 r = 8: 1.13 -> 0.89 ms.)
-  constexpr bool kNarrowPlain = sizeof(T) == 1;
+  constexpr bool kNarrowPlain = sizeof(T) == 1 && BQ == 32;
   int bc = 0, q0 = 0;
   bool wide = !ADAPT;  // adaptive trees start on 16 dwords
   auto place = [&](int m) {
-    if (!ADAPT) {  // two 64-leaf subtrees of the uniform tree, m in the middle half
-      bc = (m & ~63) - ((m & 63) < 32 ? 64 : 0);
+    if (!ADAPT) {  // BQ / 16 64-leaf subtrees of the uniform tree, m in the middle half
+      bc = (m - 2 * kBinQ + 32) & ~63;
       bc = bc < 0 ? 0 : bc;
       q0 = 0;
       wide = true;
@@ -559,7 +592,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     return window_rank_exact<T>(src, a.srs, a.w, a.h, xc, y, r, rank, L.bins, lane);
   };
   auto build = [&](int y) {
-    rebuild<T, KC>(src, a.srs, h, r, gx, ncols, L, wave_dwords, y, bc, q0, sq(), lane);
+    rebuild<T, KC, BQ>(src, a.srs, h, r, gx, ncols, L, wave_dwords, y, bc, q0, sq(), lane);
   };
   // a row this strip cannot finish: flag the tiered kernel's tile holding it
   // (that tile is recomputed whole after this launch)
@@ -594,9 +627,9 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     for (int tries = 0;; ++tries) {
       RowOut o;
       if (!wide)
-        o = row_medians<16>(L, q0, lane, r2, ncols, a.n, rank, live);
+        o = row_medians<BQ, 16>(L, q0, lane, r2, ncols, a.n, rank, live);
       else
-        o = row_medians<kBinQ>(L, q0, lane, r2, ncols, a.n, rank, live);
+        o = row_medians<BQ, BQ>(L, q0, lane, r2, ncols, a.n, rank, live);
       if (!have && o.ok) {
         res = bc + 4 * q0 + o.off;
         have = true;
@@ -610,7 +643,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         for (int qs = q0; qs < q0 + (!wide ? 16 : kBinQ); qs += 16) {
           int off16, cnt16;
           bool ok16;
-          row16(L, qs, lane, r2, rank, below, off16, ok16, cnt16);
+          row16<BQ>(L, qs, lane, r2, rank, below, off16, ok16, cnt16);
           if (!have && ok16) {
             res = bc + 4 * qs + off16;
             have = true;
@@ -627,7 +660,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         break;
       }
       if (!wide) {  // scan all 128 leaves
-        retarget<KC>(L, ncols, r2, q0, 16, 0, kBinQ, lane);
+        retarget<KC, BQ>(L, ncols, r2, q0, 16, 0, kBinQ, lane);
         q0 = 0;
         wide = true;
         continue;
@@ -677,7 +710,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         if (q1 < 0 && !ballot(live && (off < 4 * q + kMargin || off >= 4 * q + 64 - kMargin)))
           q1 = q;
       if (q1 >= 0) {
-        retarget<KC>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
+        retarget<KC, BQ>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
         q0 = q1;
         wide = false;
       }
@@ -692,7 +725,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         const bool room_hi = ballot(live && off < kMargin + 16) == 0;
         if (near_lo && room_lo && bs > 0) {
           if (q0 >= 4) {
-            retarget<KC>(L, ncols, r2, q0, 16, q0 - 4, 16, lane);
+            retarget<KC, BQ>(L, ncols, r2, q0, 16, q0 - 4, 16, lane);
             q0 -= 4;
           } else {
             place(bs + 32 - 16);
@@ -701,7 +734,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
           }
         } else if (near_hi && room_hi && bs + 64 <= maxv) {
           if (q0 + 4 <= kBinQ - 16) {
-            retarget<KC>(L, ncols, r2, q0, 16, q0 + 4, 16, lane);
+            retarget<KC, BQ>(L, ncols, r2, q0, 16, q0 + 4, 16, lane);
             q0 += 4;
           } else {
             place(bs + 32 + 16);
@@ -717,16 +750,16 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
                                 !ballot(live && (off < 64 + kMargin || off >= 128 - kMargin)))) {
       // the row's medians lie well inside one subtree: scan only that one
       const int q1 = ballot(live && off >= 64) ? 16 : 0;
-      retarget<KC>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
+      retarget<KC, BQ>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
       q0 = q1;
       wide = false;
     } else {
       // move the pair of subtrees by one subtree
       const bool near_lo = ballot(live && off < kMargin) != 0;
       const bool near_hi = ballot(live && off >= 4 * kBinQ - kMargin) != 0;
-      const bool room_lo = ballot(live && off >= 64 - kMargin) == 0;
+      const bool room_lo = ballot(live && off >= 4 * kBinQ - 64 - kMargin) == 0;
       const bool room_hi = ballot(live && off < 64 + kMargin) == 0;
-      if ((near_lo && room_lo && bc >= 64) || (near_hi && room_hi && bc + 128 <= maxv)) {
+      if ((near_lo && room_lo && bc >= 64) || (near_hi && room_hi && bc + 4 * kBinQ <= maxv)) {
         bc += near_lo ? -64 : 64;
         build(y + 1);
         rebuilt = true;
@@ -741,15 +774,15 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     for (int k = 0; k < KC; ++k) {
       const int c = lane + 64 * k;
       if (c < ncols) {
-        const Cls o = classify(vo[k], bc, q0, s);
-        const Cls i = classify(vi[k], bc, q0, s);
+        const Cls o = classify<BQ>(vo[k], bc, q0, s);
+        const Cls i = classify<BQ>(vi[k], bc, q0, s);
         const bool same = i.q == o.q;
         const uint32_t di = same ? i.inc - o.inc : i.inc;
         const uint32_t dl = i.lh - o.lh;
         uint32_t* col = L.bins + c * kPitch;
         lds_add(col + i.q, di);
         lds_add(col + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
-        lds_add(lohi_of(L, c), dl);
+        lds_add(lohi_of<BQ>(L, c), dl);
         if (c <= r2) {
           lds_add(L.base + i.q, di);
           lds_add(L.base + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
@@ -764,13 +797,13 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
 // Columns one lane holds: ceil((64 + 2r) / 64).
 constexpr int kc_for(int r) { return (64 + 2 * r + 63) / 64; }
 
-template <typename T, bool ADAPT, int KC, int WPG>
+template <typename T, bool ADAPT, int KC, int WPG, int BQ>
 __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   // the wave's index in the workgroup, as a value the compiler knows to be
   // uniform: everything derived from it (tile, rows, range) stays scalar
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  window_tile<T, ADAPT, KC>(a, (int64_t)blockIdx.x * WPG + wv, wv, lds);
+  window_tile<T, ADAPT, KC, BQ>(a, (int64_t)blockIdx.x * WPG + wv, wv, lds);
 }
 
 // Many images in one launch (uniform tree): workgroup g belongs to the first
@@ -793,25 +826,30 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window_multi(
   const int64_t first = lo > 0 ? imgs[lo - 1].group_end : 0;
   const WindowArgs a = imgs[lo].args;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  window_tile<T, false, KC>(a, (g - first) * WPG + wv, wv, lds);
+  window_tile<T, false, KC, 32>(a, (g - first) * WPG + wv, wv, lds);
 }
 
-template <typename T, bool ADAPT, int KC, int WPG>
+template <typename T, bool ADAPT, int KC, int WPG, int BQ = 32>
 hipError_t launch_k(const WindowArgs& a, hipStream_t stream) {
   const size_t lds = (size_t)WPG * a.wave_bytes;
-  const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG>;
+  const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG, BQ>;
   hipError_t e = ensure_dynamic_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (window_tiles(a) + WPG - 1) / WPG;
-  hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG>), dim3((uint32_t)grid), dim3(64 * WPG),
-                     lds, stream, a);
+  hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG, BQ>), dim3((uint32_t)grid),
+                     dim3(64 * WPG), lds, stream, a);
   return hipGetLastError();
 }
 
 template <typename T, bool ADAPT>
 hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
   const int kc = kc_for(a.r);
-  const int wpg = window_launch_wpg((int)sizeof(T), a.r);
+  const int wpg = window_launch_wpg((int)sizeof(T), a.r, a.bq);
+  if constexpr (!ADAPT) {
+    if (a.bq == 64)  // (r <= 32: two columns per lane)
+      return wpg == 4 ? launch_k<T, false, 2, 4, 64>(a, stream)
+                      : launch_k<T, false, 2, 1, 64>(a, stream);
+  }
   if (kc <= 2)
     return wpg == 4 ? launch_k<T, ADAPT, 2, 4>(a, stream) : launch_k<T, ADAPT, 2, 1>(a, stream);
   if (kc == 3) return wpg == 4 ? launch_k<T, ADAPT, 3, 4>(a, stream)
@@ -821,15 +859,23 @@ hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
 
 template <typename T, bool ADAPT>
 hipError_t prime_w() {
-  const void* ks[] = {(const void*)k_median_window<T, ADAPT, 2, 4>,
-                      (const void*)k_median_window<T, ADAPT, 2, 1>,
-                      (const void*)k_median_window<T, ADAPT, 3, 4>,
-                      (const void*)k_median_window<T, ADAPT, 3, 2>,
-                      (const void*)k_median_window<T, ADAPT, 5, 2>,
-                      (const void*)k_median_window<T, ADAPT, 5, 1>};
+  const void* ks[] = {(const void*)k_median_window<T, ADAPT, 2, 4, 32>,
+                      (const void*)k_median_window<T, ADAPT, 2, 1, 32>,
+                      (const void*)k_median_window<T, ADAPT, 3, 4, 32>,
+                      (const void*)k_median_window<T, ADAPT, 3, 2, 32>,
+                      (const void*)k_median_window<T, ADAPT, 5, 2, 32>,
+                      (const void*)k_median_window<T, ADAPT, 5, 1, 32>};
   for (const void* k : ks) {
     const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
     if (e != hipSuccess) return e;
+  }
+  if constexpr (!ADAPT) {
+    const void* k64[] = {(const void*)k_median_window<T, false, 2, 4, 64>,
+                         (const void*)k_median_window<T, false, 2, 1, 64>};
+    for (const void* k : k64) {
+      const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -840,20 +886,20 @@ int64_t window_tiles(const WindowArgs& a) { return window_tile_count(a); }
 
 // Waves per CU with workgroups of wpg waves at radius r (LDS is granted to a
 // workgroup in blocks of 1,280 bytes).
-static int waves_at(int wpg, int r) {
-  const size_t per = ((size_t)wpg * window_wave_bytes(r) + 1279) / 1280 * 1280;
+static int waves_at(int wpg, int r, int bq) {
+  const size_t per = ((size_t)wpg * window_wave_bytes(r, bq) + 1279) / 1280 * 1280;
   const int waves = (int)((size_t)kLdsLimit / per) * wpg;
   return waves < 32 ? (waves > 0 ? waves : 1) : 32;
 }
 
-int window_launch_wpg(int bytes, int r) {
+int window_launch_wpg(int bytes, int r, int bq) {
   const int kc = kc_for(r);
   if (kc <= 2) {
     // one- or four-wave workgroups, whichever lets more waves share a CU
     // (16-bit X-ray-like 4096^2 r = 15: 11 against 8 waves, 0.47 -> 0.41 ms);
     // on a tie 8-bit launches, which have four times the waves, take four
     // (8-bit low-key 8192^2 r = 8: 0.94 -> 0.87 ms)
-    const int w1 = waves_at(1, r), w4 = waves_at(4, r);
+    const int w1 = waves_at(1, r, bq), w4 = waves_at(4, r, bq);
     return bytes == 1 ? (w4 >= w1 ? 4 : 1) : (w1 >= w4 ? 1 : 4);
   }
   const int wpg = window_waves_per_group(r);
@@ -861,7 +907,16 @@ int window_launch_wpg(int bytes, int r) {
   return wpg >= 2 ? 2 : 1;
 }
 
-int window_waves_per_cu(int bytes, int r) { return waves_at(window_launch_wpg(bytes, r), r); }
+int window_waves_per_cu(int bytes, int r, int bq) {
+  return waves_at(window_launch_wpg(bytes, r, bq), r, bq);
+}
+
+int window_bq(int bytes, int r, bool adaptive) {
+  // 16-bit windows of r <= 7 on the uniform tree: 256 grey levels per column,
+  // as their rows' medians spread over more than 128 (X-ray-like 4096^2
+  // r = 5: 0.69 against 1.73 ms, r = 7 0.59 against 0.69)
+  return bytes == 2 && !adaptive && r <= 7 ? 64 : 32;
+}
 
 int window_multi_waves(int bytes, int r_max) {
   return kc_for(r_max) > 2 ? 0 : bytes == 2 ? 1 : 4;
@@ -872,7 +927,7 @@ hipError_t launch_window_multi(const WindowImage* d_imgs, int n, int64_t groups,
   if (n <= 0 || groups <= 0) return hipSuccess;
   if (kc_for(r_max) > 2 || groups > 0x7fffffffLL) return hipErrorInvalidValue;
   const int wpg = window_multi_waves(bytes, r_max);
-  const size_t lds = (size_t)wpg * window_wave_bytes(r_max);
+  const size_t lds = (size_t)wpg * window_wave_bytes(r_max, 32);
   const void* kern = bytes == 2 ? (const void*)k_median_window_multi<uint16_t, 2, 1>
                                 : (const void*)k_median_window_multi<uint8_t, 2, 4>;
   hipError_t e = ensure_dynamic_lds(kern, lds);
@@ -886,14 +941,14 @@ hipError_t launch_window_multi(const WindowImage* d_imgs, int n, int64_t groups,
   return hipGetLastError();
 }
 
-size_t window_wave_bytes(int r) {
+size_t window_wave_bytes(int r, int bq) {
   const int ncols = 64 + 2 * r;
-  // + base and a block of zeros (kPitch dwords each)
-  return window_base_offset(ncols) + (size_t)2 * kPitch * 4;
+  // + base and a block of zeros (bq + 4 dwords each)
+  return window_base_offset(ncols + 2, bq);
 }
 
 int window_waves_per_group(int r) {
-  const size_t b = window_wave_bytes(r);
+  const size_t b = window_wave_bytes(r, 32);
   return 4 * b <= (size_t)kLdsLimit ? 4 : 2 * b <= (size_t)kLdsLimit ? 2 : 1;
 }
 
