@@ -158,12 +158,23 @@ def test_rows_left_to_the_tiered_kernel(hrrm, ctx):
 
 @pytest.mark.parametrize("rank_of", [0.0, 0.1, 0.5, 0.9, 1.0])
 def test_rank_filters(hrrm, ctx, rank_of):
-    r = 9
-    n = (2 * r + 1) ** 2
-    k = min(n - 1, int(rank_of * n))
     img = datagen.xray_u16(120, 250, seed=390)
-    for variant in ("plain", "adaptive"):
-        _check(hrrm, ctx, "rank", img, r, variant, rank=k)
+    for r in (5, 9):  # 256 and 128 grey levels per column (uniform tree)
+        n = (2 * r + 1) ** 2
+        k = min(n - 1, int(rank_of * n))
+        for variant in ("plain", "adaptive"):
+            _check(hrrm, ctx, "rank", img, r, variant, rank=k)
+
+
+@pytest.mark.parametrize("r", [4, 7])
+def test_u16_wide_columns_move(hrrm, ctx, r):
+    # 16-bit images at r <= 7 (256 grey levels per column, uniform tree) whose
+    # row medians drift across the window of grey levels: steep ramps move it
+    # by whole subtrees and rebuild it
+    y, x = np.mgrid[0:150, 0:320]
+    for slope in (1.0, 4.0):
+        img = np.clip(900 + slope * x + 2.0 * y + (x * 7 + y * 13) % 23, 0, 65535).astype(np.uint16)
+        _check(hrrm, ctx, "u16 ramp %.0f" % slope, img, r, "plain")
 
 
 def test_strided_rows(hrrm, ctx):
@@ -180,6 +191,16 @@ def test_strided_rows(hrrm, ctx):
     finally:
         ctx.set_tile(hrrm.U16, 2, 11, "adaptive")
     want = oracle.median2d(img, 11)
+    assert np.array_equal(got[:, :230], want), first_mismatch(got[:, :230], want)
+    assert not got[:, 230:].any()
+    ctx.set_tile(hrrm.U16, 2, 5, "plain", window_rows=16)
+    try:
+        out = torch.zeros((100, 300), dtype=torch.uint16, device="cuda:0")
+        ctx.median2d(src, 5, variant="plain", out=out[:, :230])
+        got = to_host(out)
+    finally:
+        ctx.set_tile(hrrm.U16, 2, 5, "plain")
+    want = oracle.median2d(img, 5)
     assert np.array_equal(got[:, :230], want), first_mismatch(got[:, :230], want)
     assert not got[:, 230:].any()
 
