@@ -576,13 +576,13 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
       q0 = 0;
       wide = true;
     } else if (wide) {
-      bc = (m - 64) & ~15;
+      bc = (m - 2 * kBinQ) & ~15;
       bc = bc < 0 ? 0 : bc;
       q0 = 0;
-    } else {  // 64 scanned leaves centred on m, inside the 128 leaves
+    } else {  // 64 scanned leaves centred on m, in the middle of the 4 BQ leaves
       int bs = (m - 32 + 8) & ~15;
       bs = bs < 0 ? 0 : bs;
-      bc = bs - 32 < 0 ? 0 : bs - 32;
+      bc = bs - (2 * kBinQ - 32) < 0 ? 0 : bs - (2 * kBinQ - 32);
       q0 = (bs - bc) >> 2;
     }
   };
@@ -845,11 +845,8 @@ template <typename T, bool ADAPT>
 hipError_t launch_w(const WindowArgs& a, hipStream_t stream) {
   const int kc = kc_for(a.r);
   const int wpg = window_launch_wpg((int)sizeof(T), a.r, a.bq);
-  if constexpr (!ADAPT) {
-    if (a.bq == 64)  // (r <= 32: two columns per lane)
-      return wpg == 4 ? launch_k<T, false, 2, 4, 64>(a, stream)
-                      : launch_k<T, false, 2, 1, 64>(a, stream);
-  }
+  if (a.bq == 64)  // (r <= 32: two columns per lane)
+    return wpg == 4 ? launch_k<T, ADAPT, 2, 4, 64>(a, stream) : launch_k<T, ADAPT, 2, 1, 64>(a, stream);
   if (kc <= 2)
     return wpg == 4 ? launch_k<T, ADAPT, 2, 4>(a, stream) : launch_k<T, ADAPT, 2, 1>(a, stream);
   if (kc == 3) return wpg == 4 ? launch_k<T, ADAPT, 3, 4>(a, stream)
@@ -869,13 +866,11 @@ hipError_t prime_w() {
     const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
     if (e != hipSuccess) return e;
   }
-  if constexpr (!ADAPT) {
-    const void* k64[] = {(const void*)k_median_window<T, false, 2, 4, 64>,
-                         (const void*)k_median_window<T, false, 2, 1, 64>};
-    for (const void* k : k64) {
-      const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
-      if (e != hipSuccess) return e;
-    }
+  const void* k64[] = {(const void*)k_median_window<T, ADAPT, 2, 4, 64>,
+                       (const void*)k_median_window<T, ADAPT, 2, 1, 64>};
+  for (const void* k : k64) {
+    const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -912,10 +907,12 @@ int window_waves_per_cu(int bytes, int r, int bq) {
 }
 
 int window_bq(int bytes, int r, bool adaptive) {
-  // 16-bit windows of r <= 7 on the uniform tree: 256 grey levels per column,
-  // as their rows' medians spread over more than 128 (X-ray-like 4096^2
-  // r = 5: 0.69 against 1.73 ms, r = 7 0.59 against 0.69)
-  return bytes == 2 && !adaptive && r <= 7 ? 64 : 32;
+  // 16-bit windows of r <= 7: 256 grey levels per column, as their rows'
+  // medians spread over more than 128 (X-ray-like 4096^2 r = 5: uniform tree
+  // 0.69 against 1.73 ms, adaptive 0.82 against 1.71; r = 7 0.59 against
+  // 0.69, adaptive 0.67 against 1.11); the adaptive tree at r = 1 keeps 128
+  // (1.27 against 5.3 ms: its narrow ranges there miss more often)
+  return bytes == 2 && r <= 7 && (!adaptive || r >= 2) ? 64 : 32;
 }
 
 int window_multi_waves(int bytes, int r_max) {
