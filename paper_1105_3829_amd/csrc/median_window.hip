@@ -53,16 +53,19 @@
 namespace hrrm {
 namespace {
 
-// Layout of a column's counters, for BQ dwords of byte counters (4 BQ grey
-// levels: 128 or 256), written out in each function as
-//   kBinQ = BQ          dwords of byte counters per column
-//   kPitch = BQ + 4     dwords per column (= 4 mod 32: the 128-bit reads of 8
-//                       consecutive lanes hit distinct banks)
-//   kLohi = BQ          dword of the lo/hi counts of a column (and of the base)
-//   kSink = BQ + 1      pad dword that takes the zero updates of values outside
-//                       the leaves
-//   kSpare = BQ + 2     pad dwords BQ + 2, BQ + 3 of columns 0..15: row16's
-//                       16-bit counts
+// Layout of a column's counters for BQ dwords of byte counters (4 BQ grey
+// levels: 128 or 256).
+template <int BQ>
+struct Layout {
+  static constexpr int kBinQ = BQ;       // dwords of byte counters per column
+  static constexpr int kPitch = BQ + 4;  // dwords per column (= 4 mod 32: the 128-bit
+                                         // reads of 8 consecutive lanes hit distinct banks)
+  static constexpr int kLohi = BQ;       // lo/hi counts of a column (and of the base)
+  static constexpr int kSink = BQ + 1;   // pad dword taking the zero updates of values
+                                         // outside the leaves
+  static constexpr int kSpare = BQ + 2;  // pad dwords BQ + 2, BQ + 3 of columns 0..15:
+                                         // row16's 16-bit counts
+};
 constexpr int kMaxPasses = 6;  // passes over one row before it is left to the tiered kernel
 
 // Where a value goes: leaf dword q with byte increment inc (values outside
@@ -75,12 +78,11 @@ struct Cls {
 
 template <int BQ>
 __device__ __forceinline__ Cls classify(int v, int bc, int q0, int sq) {
-  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
-  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
+  using Y = Layout<BQ>;
   const int rel = v - bc;
-  const bool in = (uint32_t)rel < 4u * kBinQ;
+  const bool in = (uint32_t)rel < 4u * Y::kBinQ;
   Cls c;
-  c.q = in ? rel >> 2 : kSink;
+  c.q = in ? rel >> 2 : Y::kSink;
   c.inc = in ? 1u << ((rel & 3) << 3) : 0u;
   // below the scanned dwords (also below the leaves), or above them
   c.lh = rel < 4 * q0 ? 1u : (rel >= 4 * (q0 + sq) ? 0x10000u : 0u);
@@ -182,12 +184,11 @@ __device__ __forceinline__ bool step(uint32_t c, uint32_t& k) {
 template <int BQ, int SQ>
 __device__ __forceinline__ vu<SQ> window_counts(const WaveLds& L, int q0, int lane, int r2,
                                                 int ncols, uint32_t& wl) {
-  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
-  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
+  using Y = Layout<BQ>;
   const int ci = lane ? lane + r2 : ncols;      // column x + r
   const int co = lane ? lane - 1 : ncols + 1;   // column x - r - 1
-  const uint32_t* pi = L.bins + ci * kPitch + q0;
-  const uint32_t* po = L.bins + co * kPitch + q0;
+  const uint32_t* pi = L.bins + ci * Y::kPitch + q0;
+  const uint32_t* po = L.bins + co * Y::kPitch + q0;
   vu<SQ> W;
 #pragma unroll
   for (int k = 0; k < SQ; k += 4) {
@@ -331,8 +332,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
                                         const int (&gx)[KC], int ncols, const WaveLds& L,
                                         int wave_dwords, int y, int bc, int q0, int sq,
                                         int lane) {
-  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
-  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
+  using Y = Layout<BQ>;
   uint4* z = (uint4*)L.bins;
   for (int i = lane; i < wave_dwords / 4; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
   __builtin_amdgcn_wave_barrier();
@@ -358,7 +358,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
         for (int t = 0; t < kBatch; ++t) {
           if (j0 + t <= r) {
             const Cls cl = classify<BQ>(v[t], bc, q0, sq);
-            lds_add(L.bins + c * kPitch + cl.q, cl.inc);
+            lds_add(L.bins + c * Y::kPitch + cl.q, cl.inc);
             lohi[k] += cl.lh;
           }
         }
@@ -370,11 +370,11 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
     if (lane + 64 * k < ncols) *lohi_of<BQ>(L, lane + 64 * k) = lohi[k];
   __builtin_amdgcn_wave_barrier();
   // base dword i (leaf dwords, then lo/hi at kLohi = kBinQ) by lane i % 64
-  for (int i = lane; i <= kBinQ; i += 64) {
+  for (int i = lane; i <= Y::kBinQ; i += 64) {
     uint32_t s = 0;
-    if (i < kBinQ) {
+    if (i < Y::kBinQ) {
 #pragma unroll 8
-      for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * kPitch + i];
+      for (int c = 0; c <= 2 * r; ++c) s += L.bins[c * Y::kPitch + i];
     } else {
 #pragma unroll 8
       for (int c = 0; c <= 2 * r; ++c) s += *lohi_of<BQ>(L, c);
@@ -393,8 +393,7 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
 template <int KC, int BQ>
 __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, int q0, int s0,
                                          int q1, int s1, int lane) {
-  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
-  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
+  using Y = Layout<BQ>;
   const int la = q0 < q1 ? q0 : q1, lb = q0 < q1 ? q1 : q0;
   const int e0 = q0 + s0, e1 = q1 + s1;
   const int ha = e0 < e1 ? e0 : e1, hb = e0 < e1 ? e1 : e0;
@@ -402,7 +401,7 @@ __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, in
   for (int k = 0; k < KC; ++k) {
     const int c = lane + 64 * k;
     if (c < ncols) {
-      const uint32_t* col = L.bins + c * kPitch;
+      const uint32_t* col = L.bins + c * Y::kPitch;
       uint32_t lo = 0, hi = 0;
       for (int q = la; q < lb; q += 4) {
         const uint4 u = *(const uint4*)(col + q);
@@ -426,7 +425,7 @@ __device__ __forceinline__ void retarget(const WaveLds& L, int ncols, int r2, in
     if (c <= r2) s += *lohi_of<BQ>(L, c);
   }
   s = wave_scan(s);
-  if (lane == 63) L.base[kLohi] = s;
+  if (lane == 63) L.base[Y::kLohi] = s;
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -466,20 +465,19 @@ __device__ __forceinline__ RowOut row_medians(const WaveLds& L, int q0, int lane
 template <int BQ>
 __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2, int rank,
                                       int below, int& off, bool& ok, int& cnt) {
-  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
-  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
+  using Y = Layout<BQ>;
   // the first window's counts, summed again from its 2r + 1 columns
   if (lane < 32) {
     uint32_t acc = 0;
     const int q = qs + (lane >> 1), sh = (lane & 1) * 8;
-    for (int c = 0; c <= r2; ++c) acc += (L.bins[c * kPitch + q] >> sh) & 0x00ff00ffu;
-    L.bins[(lane >> 1) * kPitch + kSpare + (lane & 1)] = acc;
+    for (int c = 0; c <= r2; ++c) acc += (L.bins[c * Y::kPitch + q] >> sh) & 0x00ff00ffu;
+    L.bins[(lane >> 1) * Y::kPitch + Y::kSpare + (lane & 1)] = acc;
   }
   __builtin_amdgcn_wave_barrier();
   const int ci = lane + r2;
   const int co = lane == 0 ? ci : lane - 1;
-  const uint32_t* pi = L.bins + ci * kPitch + qs;
-  const uint32_t* po = L.bins + co * kPitch + qs;
+  const uint32_t* pi = L.bins + ci * Y::kPitch + qs;
+  const uint32_t* po = L.bins + co * Y::kPitch + qs;
   // F[2q]: leaves 4q and 4q + 2, F[2q + 1]: leaves 4q + 1 and 4q + 3
   vu<32> F;
 #pragma unroll
@@ -490,7 +488,7 @@ __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int q = k + i;
-      const uint2 b16 = *(const uint2*)(L.bins + q * kPitch + kSpare);
+      const uint2 b16 = *(const uint2*)(L.bins + q * Y::kPitch + Y::kSpare);
       F[2 * q] = b16.x + wave_scan((av[i] & 0x00ff00ffu) - (bv[i] & 0x00ff00ffu));
       F[2 * q + 1] =
           b16.y + wave_scan(((av[i] >> 8) & 0x00ff00ffu) - ((bv[i] >> 8) & 0x00ff00ffu));
@@ -532,8 +530,7 @@ __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2
 template <typename T, bool ADAPT, int KC, int BQ>
 __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, int wv,
                                             uint8_t* lds) {
-  constexpr int kBinQ = BQ, kPitch = BQ + 4, kLohi = BQ, kSink = BQ + 1, kSpare = BQ + 2;
-  (void)kBinQ, (void)kPitch, (void)kLohi, (void)kSink, (void)kSpare;
+  using Y = Layout<BQ>;
   const int lane = threadIdx.x & 63;
   int strip, y0, y1;
   if (!window_tile_rows(a, tile, strip, y0, y1)) return;
@@ -571,22 +568,22 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   bool wide = !ADAPT;  // adaptive trees start on 16 dwords
   auto place = [&](int m) {
     if (!ADAPT) {  // BQ / 16 64-leaf subtrees of the uniform tree, m in the middle half
-      bc = (m - 2 * kBinQ + 32) & ~63;
+      bc = (m - 2 * Y::kBinQ + 32) & ~63;
       bc = bc < 0 ? 0 : bc;
       q0 = 0;
       wide = true;
     } else if (wide) {
-      bc = (m - 2 * kBinQ) & ~15;
+      bc = (m - 2 * Y::kBinQ) & ~15;
       bc = bc < 0 ? 0 : bc;
       q0 = 0;
     } else {  // 64 scanned leaves centred on m, in the middle of the 4 BQ leaves
       int bs = (m - 32 + 8) & ~15;
       bs = bs < 0 ? 0 : bs;
-      bc = bs - (2 * kBinQ - 32) < 0 ? 0 : bs - (2 * kBinQ - 32);
+      bc = bs - (2 * Y::kBinQ - 32) < 0 ? 0 : bs - (2 * Y::kBinQ - 32);
       q0 = (bs - bc) >> 2;
     }
   };
-  auto sq = [&]() { return wide ? kBinQ : 16; };
+  auto sq = [&]() { return wide ? Y::kBinQ : 16; };
   auto estimate = [&](int lane_of, int y) -> int {
     const int xc = x0 + lane_of < w ? x0 + lane_of : w - 1;
     return window_rank_exact<T>(src, a.srs, a.w, a.h, xc, y, r, rank, L.bins, lane);
@@ -640,7 +637,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         // a leaf count passed 255: count the scanned leaves again with
         // 16-bit fields, 64 leaves at a time
         int below = o.lo;
-        for (int qs = q0; qs < q0 + (!wide ? 16 : kBinQ); qs += 16) {
+        for (int qs = q0; qs < q0 + (!wide ? 16 : Y::kBinQ); qs += 16) {
           int off16, cnt16;
           bool ok16;
           row16<BQ>(L, qs, lane, r2, rank, below, off16, ok16, cnt16);
@@ -660,7 +657,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         break;
       }
       if (!wide) {  // scan all 128 leaves
-        retarget<KC, BQ>(L, ncols, r2, q0, 16, 0, kBinQ, lane);
+        retarget<KC, BQ>(L, ncols, r2, q0, 16, 0, Y::kBinQ, lane);
         q0 = 0;
         wide = true;
         continue;
@@ -706,11 +703,11 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
       // back to 16 scanned dwords once the row's medians fit them with margins
       int q1 = -1;
 #pragma unroll
-      for (int q = 0; q <= kBinQ - 16; q += 4)
+      for (int q = 0; q <= Y::kBinQ - 16; q += 4)
         if (q1 < 0 && !ballot(live && (off < 4 * q + kMargin || off >= 4 * q + 64 - kMargin)))
           q1 = q;
       if (q1 >= 0) {
-        retarget<KC, BQ>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
+        retarget<KC, BQ>(L, ncols, r2, 0, Y::kBinQ, q1, 16, lane);
         q0 = q1;
         wide = false;
       }
@@ -733,7 +730,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
             rebuilt = true;
           }
         } else if (near_hi && room_hi && bs + 64 <= maxv) {
-          if (q0 + 4 <= kBinQ - 16) {
+          if (q0 + 4 <= Y::kBinQ - 16) {
             retarget<KC, BQ>(L, ncols, r2, q0, 16, q0 + 4, 16, lane);
             q0 += 4;
           } else {
@@ -750,16 +747,16 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
                                 !ballot(live && (off < 64 + kMargin || off >= 128 - kMargin)))) {
       // the row's medians lie well inside one subtree: scan only that one
       const int q1 = ballot(live && off >= 64) ? 16 : 0;
-      retarget<KC, BQ>(L, ncols, r2, 0, kBinQ, q1, 16, lane);
+      retarget<KC, BQ>(L, ncols, r2, 0, Y::kBinQ, q1, 16, lane);
       q0 = q1;
       wide = false;
     } else {
       // move the pair of subtrees by one subtree
       const bool near_lo = ballot(live && off < kMargin) != 0;
-      const bool near_hi = ballot(live && off >= 4 * kBinQ - kMargin) != 0;
-      const bool room_lo = ballot(live && off >= 4 * kBinQ - 64 - kMargin) == 0;
+      const bool near_hi = ballot(live && off >= 4 * Y::kBinQ - kMargin) != 0;
+      const bool room_lo = ballot(live && off >= 4 * Y::kBinQ - 64 - kMargin) == 0;
       const bool room_hi = ballot(live && off < 64 + kMargin) == 0;
-      if ((near_lo && room_lo && bc >= 64) || (near_hi && room_hi && bc + 4 * kBinQ <= maxv)) {
+      if ((near_lo && room_lo && bc >= 64) || (near_hi && room_hi && bc + 4 * Y::kBinQ <= maxv)) {
         bc += near_lo ? -64 : 64;
         build(y + 1);
         rebuilt = true;
@@ -779,14 +776,14 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         const bool same = i.q == o.q;
         const uint32_t di = same ? i.inc - o.inc : i.inc;
         const uint32_t dl = i.lh - o.lh;
-        uint32_t* col = L.bins + c * kPitch;
+        uint32_t* col = L.bins + c * Y::kPitch;
         lds_add(col + i.q, di);
-        lds_add(col + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
+        lds_add(col + (same ? Y::kSink : o.q), same ? 0u : 0u - o.inc);
         lds_add(lohi_of<BQ>(L, c), dl);
         if (c <= r2) {
           lds_add(L.base + i.q, di);
-          lds_add(L.base + (same ? kSink : o.q), same ? 0u : 0u - o.inc);
-          lds_add(L.base + kLohi, dl);
+          lds_add(L.base + (same ? Y::kSink : o.q), same ? 0u : 0u - o.inc);
+          lds_add(L.base + Y::kLohi, dl);
         }
       }
     }
