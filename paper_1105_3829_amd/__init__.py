@@ -339,6 +339,7 @@ class Server:
         check(lib().hrrm_server_create(ctx.handle, budget_bytes, max_inflight, max_queue,
                                        self.PER_IMAGE if per_image else 0, ctypes.byref(self._h)))
         self._keep = {}
+        self._drain_bufs = None  # (max_n, tickets, results), reused by drain()
 
     def submit(self, img, r: int) -> int:
         torch = _torch()
@@ -374,8 +375,9 @@ class Server:
 
     def drain(self, max_n: int = 4096):
         """Done tickets not reported before: list of (ticket, result dict)."""
-        tk = (ctypes.c_uint64 * max_n)()
-        rs = (_Result * max_n)()
+        if self._drain_bufs is None or self._drain_bufs[0] != max_n:
+            self._drain_bufs = (max_n, (ctypes.c_uint64 * max_n)(), (_Result * max_n)())
+        _, tk, rs = self._drain_bufs
         n = check(lib().hrrm_server_drain(self._h, tk, rs, max_n))
         out = []
         for i in range(n):

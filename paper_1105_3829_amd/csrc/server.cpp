@@ -14,6 +14,9 @@
 //      image) - alternating between two compute streams, so a batch that
 //      arrives while another runs starts on the device as soon as workgroups
 //      free up.
+// Only the bookkeeping shared with the API calls (requests, queue, arena)
+// runs under the server's lock; uploads, launches and event queries do not,
+// so a submit() never waits behind a large batch being launched.
 // Output buffers stay owned by the server until release().
 #include <hip/hip_runtime.h>
 
@@ -57,6 +60,17 @@ struct Running {
   std::vector<uint64_t> tickets;
 };
 
+// An admitted request as the worker needs it outside the lock: its ticket,
+// its image in the arena and where its input comes from.
+struct Staged {
+  uint64_t tk;
+  hrrm_image im;
+  char* dev_in;  // im.src, writable
+  const void* src;
+  int64_t src_row_stride;
+  size_t in_bytes;
+};
+
 }  // namespace
 
 struct Server {
@@ -70,12 +84,14 @@ struct Server {
   hipStream_t comp[kStreams] = {nullptr, nullptr};
   int next_stream = 0;
   std::mutex mu;
+  // under mu (shared with the API calls)
   std::unordered_map<uint64_t, Item> items;
   std::deque<uint64_t> queue;
-  std::vector<uint64_t> staged;
-  std::vector<Running> running;
   std::deque<uint64_t> finished;  // done tickets not yet reported by drain()
   int inflight = 0;
+  // the worker's own (uploads issued, not yet launched; batches on the device)
+  std::vector<Staged> staged;
+  std::vector<Running> running;
   uint64_t next_ticket = 1;
   std::atomic<bool> stop{false};
   std::thread worker;
@@ -84,79 +100,113 @@ struct Server {
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
-  bool step();  // one pass of the loop, under the lock; true if anything happened
+  bool step();  // one pass of the loop; true if anything happened
+  void finish(const std::vector<uint64_t>& tks, int status, bool release_input);  // under mu
   void loop();
 };
 
 static size_t bpp(int dtype) { return dtype == HRRM_U8 ? 1 : 2; }
 
+// Marks the tickets done with `status` at the current time (under mu).
+void Server::finish(const std::vector<uint64_t>& tks, int status, bool release_input) {
+  const double t = now();
+  for (uint64_t tk : tks) {
+    auto it = items.find(tk);
+    if (it == items.end()) continue;
+    Item& r = it->second;
+    if (r.status == HRRM_OK) r.status = status;
+    r.st = St::Done;
+    r.t_done = t;
+    if (release_input) arena.release(r.off_in, r.in_bytes);
+    finished.push_back(tk);
+  }
+}
+
+// One pass of the worker.  Only the bookkeeping shared with the API calls
+// (items, queue, arena, finished) runs under mu; the event queries, uploads
+// and launches do not, so submit() and drain() never wait behind them.
 bool Server::step() {
   bool did = false;
   // 1. retire finished batches
+  std::vector<uint64_t> done;
   for (size_t i = 0; i < running.size();) {
     if (hipEventQuery(running[i].ev) == hipSuccess) {
-      const double t = now();
-      for (uint64_t tk : running[i].tickets) {
-        auto it = items.find(tk);
-        if (it == items.end()) continue;
-        it->second.st = St::Done;
-        it->second.t_done = t;
-        arena.release(it->second.off_in, it->second.in_bytes);
-        finished.push_back(tk);
-      }
+      done.insert(done.end(), running[i].tickets.begin(), running[i].tickets.end());
       (void)hipEventDestroy(running[i].ev);
       running.erase(running.begin() + i);
-      did = true;
     } else {
       ++i;
     }
   }
   // 2. admission (the rule itself is host_logic.hpp's plan_admission)
-  if (!queue.empty() && inflight < max_inflight) {
-    std::vector<std::pair<size_t, size_t>> need;
-    need.reserve(queue.size());
-    for (uint64_t tk : queue) {
-      const Item& r = items[tk];
-      need.emplace_back(r.in_bytes, r.out_bytes);
-    }
-    const std::vector<Admitted> plan =
-        plan_admission(arena, need, max_inflight - inflight, kBypass);
-    std::vector<bool> taken(queue.size(), false);
-    for (const Admitted& p : plan) {
-      const uint64_t tk = queue[p.index];
-      Item& r = items[tk];
-      taken[p.index] = true;
-      r.off_in = p.off_in;
-      r.off_out = p.off_out;
-      const size_t b = bpp(r.req.dtype);
-      // packed rows: one linear copy (full link speed from pinned memory);
-      // strided rows: a 2-D copy, which the runtime performs far more slowly
-      hipError_t e =
-          r.req.src_row_stride == r.req.width
-              ? hipMemcpyAsync(base + r.off_in, r.req.src, r.in_bytes, hipMemcpyHostToDevice, copy)
-              : hipMemcpy2DAsync(base + r.off_in, (size_t)r.req.width * b, r.req.src,
-                                 (size_t)r.req.src_row_stride * b, (size_t)r.req.width * b,
-                                 (size_t)r.req.height, hipMemcpyHostToDevice, copy);
-      r.st = St::Admitted;
-      r.t_admit = now();
-      ++inflight;
-      if (e != hipSuccess) {  // the request fails; its input buffer is returned at once
-        r.status = HRRM_EDEVICE;
-        r.st = St::Done;
-        r.t_done = r.t_admit;
-        arena.release(r.off_in, r.in_bytes);
-        finished.push_back(tk);
-      } else {
-        staged.push_back(tk);
-      }
+  std::vector<Staged> admitted;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if (!done.empty()) {
+      finish(done, HRRM_OK, true);
       did = true;
     }
-    if (!plan.empty()) {
-      std::deque<uint64_t> rest;
-      for (size_t i = 0; i < queue.size(); ++i)
-        if (!taken[i]) rest.push_back(queue[i]);
-      queue.swap(rest);
+    if (!queue.empty() && inflight < max_inflight) {
+      std::vector<std::pair<size_t, size_t>> need;
+      need.reserve(queue.size());
+      for (uint64_t tk : queue) {
+        const Item& r = items[tk];
+        need.emplace_back(r.in_bytes, r.out_bytes);
+      }
+      const std::vector<Admitted> plan =
+          plan_admission(arena, need, max_inflight - inflight, kBypass);
+      std::vector<bool> taken(queue.size(), false);
+      const double t = now();
+      for (const Admitted& p : plan) {
+        const uint64_t tk = queue[p.index];
+        Item& r = items[tk];
+        taken[p.index] = true;
+        r.off_in = p.off_in;
+        r.off_out = p.off_out;
+        r.st = St::Admitted;
+        r.t_admit = t;
+        ++inflight;
+        hrrm_image im{};
+        im.src = base + r.off_in;
+        im.dst = base + r.off_out;
+        im.width = r.req.width;
+        im.height = r.req.height;
+        im.src_row_stride = r.req.width;
+        im.dst_row_stride = r.req.width;
+        im.dtype = r.req.dtype;
+        im.r = r.req.r;
+        admitted.push_back(
+            Staged{tk, im, base + r.off_in, r.req.src, r.req.src_row_stride, r.in_bytes});
+      }
+      if (!plan.empty()) {
+        std::deque<uint64_t> rest;
+        for (size_t i = 0; i < queue.size(); ++i)
+          if (!taken[i]) rest.push_back(queue[i]);
+        queue.swap(rest);
+        did = true;
+      }
     }
+  }
+  // uploads on the copy stream: packed rows as one linear copy (full link
+  // speed from pinned memory); strided rows as a 2-D copy, which the runtime
+  // performs far more slowly
+  std::vector<uint64_t> failed;
+  for (const Staged& a : admitted) {
+    const size_t b = bpp(a.im.dtype);
+    const hipError_t e =
+        a.src_row_stride == a.im.width
+            ? hipMemcpyAsync(a.dev_in, a.src, a.in_bytes, hipMemcpyHostToDevice, copy)
+            : hipMemcpy2DAsync(a.dev_in, (size_t)a.im.width * b, a.src,
+                               (size_t)a.src_row_stride * b, (size_t)a.im.width * b,
+                               (size_t)a.im.height, hipMemcpyHostToDevice, copy);
+    if (e != hipSuccess)
+      failed.push_back(a.tk);  // the request fails; its input buffer is returned at once
+    else
+      staged.push_back(a);
+  }
+  if (!failed.empty()) {
+    std::lock_guard<std::mutex> g(mu);
+    finish(failed, HRRM_EDEVICE, true);
   }
   // 3. launch what was admitted
   if (!staged.empty() && (int)running.size() < kStreams) {
@@ -169,20 +219,14 @@ bool Server::step() {
               hipStreamWaitEvent(comp[s], up, 0) == hipSuccess;
     int rc = ok ? HRRM_OK : HRRM_EDEVICE;
     std::vector<hrrm_image> imgs;
+    std::vector<uint64_t> tks;
     imgs.reserve(staged.size());
-    for (uint64_t tk : staged) {
-      const Item& r = items[tk];
-      hrrm_image im{};
-      im.src = base + r.off_in;
-      im.dst = base + r.off_out;
-      im.width = r.req.width;
-      im.height = r.req.height;
-      im.src_row_stride = r.req.width;
-      im.dst_row_stride = r.req.width;
-      im.dtype = r.req.dtype;
-      im.r = r.req.r;
-      imgs.push_back(im);
+    tks.reserve(staged.size());
+    for (const Staged& a : staged) {
+      imgs.push_back(a.im);
+      tks.push_back(a.tk);
     }
+    staged.clear();
     if (rc == HRRM_OK) {
       if (mode == 0) {
         for (size_t i = 0; i < imgs.size() && rc == HRRM_OK; i += hrrm_batch_capacity()) {
@@ -206,20 +250,12 @@ bool Server::step() {
       // their uploads are complete
       (void)hipStreamSynchronize(copy);
       (void)hipStreamSynchronize(comp[s]);
-      const double t = now();
-      for (uint64_t tk : staged) {
-        Item& r = items[tk];
-        r.status = rc != HRRM_OK ? rc : HRRM_EDEVICE;
-        r.st = St::Done;
-        r.t_done = t;
-        arena.release(r.off_in, r.in_bytes);
-        finished.push_back(tk);
-      }
       if (ev) (void)hipEventDestroy(ev);
+      std::lock_guard<std::mutex> g(mu);
+      finish(tks, rc != HRRM_OK ? rc : HRRM_EDEVICE, true);
     } else {
-      running.push_back(Running{ev, staged});
+      running.push_back(Running{ev, std::move(tks)});
     }
-    staged.clear();
     did = true;
   }
   return did;
@@ -228,12 +264,13 @@ bool Server::step() {
 void Server::loop() {
   (void)hipSetDevice(ctx->device);
   for (;;) {
-    bool did, idle;
+    const bool did = step();
+    bool idle;
     {
       std::lock_guard<std::mutex> g(mu);
-      did = step();
-      idle = queue.empty() && staged.empty() && running.empty();
+      idle = queue.empty();
     }
+    idle = idle && staged.empty() && running.empty();
     if (stop.load() && idle) break;
     if (!did) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
