@@ -339,7 +339,8 @@ class Server:
         check(lib().hrrm_server_create(ctx.handle, budget_bytes, max_inflight, max_queue,
                                        self.PER_IMAGE if per_image else 0, ctypes.byref(self._h)))
         self._keep = {}
-        self._drain_bufs = None  # (max_n, tickets, results), reused by drain()
+        # per calling thread: (max_n, tickets, results), reused by drain()
+        self._drain_tls = threading.local()
 
     def submit(self, img, r: int) -> int:
         torch = _torch()
@@ -375,9 +376,11 @@ class Server:
 
     def drain(self, max_n: int = 4096):
         """Done tickets not reported before: list of (ticket, result dict)."""
-        if self._drain_bufs is None or self._drain_bufs[0] != max_n:
-            self._drain_bufs = (max_n, (ctypes.c_uint64 * max_n)(), (_Result * max_n)())
-        _, tk, rs = self._drain_bufs
+        bufs = getattr(self._drain_tls, "bufs", None)
+        if bufs is None or bufs[0] != max_n:
+            bufs = (max_n, (ctypes.c_uint64 * max_n)(), (_Result * max_n)())
+            self._drain_tls.bufs = bufs
+        _, tk, rs = bufs
         n = check(lib().hrrm_server_drain(self._h, tk, rs, max_n))
         out = []
         for i in range(n):

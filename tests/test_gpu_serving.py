@@ -212,6 +212,63 @@ def test_server_results_mix_equal_alone(hrrm, per_image):
         assert np.array_equal(o, oracle.median2d(img, r)), (img.shape, r)
 
 
+def test_server_concurrent_clients(hrrm):
+    # four client threads submit, poll and release at once while a fifth
+    # drains: the worker uploads and launches outside the lock these calls
+    # take, and every result must still equal the oracle's
+    import threading
+    ctx = hrrm.Context(0)
+    srv = hrrm.Server(ctx, 1 << 30)
+    jobs = [_mixed_images(40 + k, 15) for k in range(4)]
+    announce("server", "concurrent clients", [len(j) for j in jobs])
+    results = [None] * len(jobs)
+    errors = []
+    stop = threading.Event()
+
+    def client(k):
+        try:
+            g = np.random.default_rng(k)
+            tickets = []
+            for img, r in jobs[k]:
+                tickets.append(srv.submit(img, r))
+                time.sleep(float(g.uniform(0, 0.002)))
+            outs = {}
+            deadline = time.time() + 60
+            while len(outs) < len(tickets):
+                for t in tickets:
+                    if t not in outs:
+                        res = srv.poll(t)
+                        if res is not None:
+                            assert res["status"] == 0
+                            outs[t] = srv.fetch(res).numpy()
+                            srv.release(t)
+                assert time.time() < deadline, "server did not finish"
+                time.sleep(0.001)
+            results[k] = [outs[t] for t in tickets]
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    def drainer():
+        while not stop.is_set():
+            srv.drain(64)
+            time.sleep(0.0005)
+
+    threads = [threading.Thread(target=client, args=(k,)) for k in range(len(jobs))]
+    d = threading.Thread(target=drainer)
+    d.start()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    stop.set()
+    d.join()
+    srv.close()
+    assert not errors, errors
+    for job, got in zip(jobs, results):
+        for (img, r), o in zip(job, got):
+            assert np.array_equal(o, oracle.median2d(img, r)), (img.shape, r)
+
+
 def test_server_small_budget_admits_in_turn(hrrm):
     # a budget that holds only a couple of requests at once: later requests wait
     # for earlier outputs to be released, and everything still completes
