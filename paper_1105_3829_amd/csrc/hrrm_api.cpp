@@ -147,20 +147,22 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
       } else {
         rows = r <= 5 ? 64 : r <= 31 ? 48 : 24;
       }
-    } else if (!adaptive) {
+    } else {
       // 8-bit trees need at most 17 slots: three workgroups per CU, four
       // where no subtree is counted wave-wide (the build without the matrix
-      // cores has the registers for it)
+      // cores has the registers for it); adaptive trees too (low-key
+      // 8192^2 r = 64: 7.8 -> 6.6 ms against 80 KB budgets, r = 100 8.6 ->
+      // 7.4)
       t.lds_budget = t.max_groups == 0 ? kLdsQuarter : kLdsThird;
       rows = t.max_groups == 0 ? 128 : 171;
-    } else {
-      rows = r <= 2 ? 32 : r <= 8 ? 128 : 256;
     }
-  } else if (!adaptive) {
+  } else if (!adaptive || r <= 2) {
     // measured on a 512 x 512 x 256 16-bit volume, r = 1..7: 16-bit cubes of
     // up to 125 values count every deeper tier raw at six workgroups per CU
     // (at r = 2 the medians spread over more deep subtrees than even 160 KB
-    // of slots hold well)
+    // of slots hold well); adaptive trees take the same tiles up to r = 2
+    // (r = 1 26.9 -> 14.4 ms, r = 2 60.3 -> 32.0) but not at r = 5 (165
+    // against 172 ms)
     t.max_groups = r <= 3 ? 0 : 2;
     rows = r == 2 ? 256 : r <= 3 ? 64 : 256;
     if (r <= 2 && bytes == 2) {

@@ -1530,14 +1530,15 @@ hipError_t launch_t(const MedianArgs& a, size_t lds, hipStream_t stream) {
       return hipGetLastError();
     }
   }
-  if constexpr (!ADAPT) {
-    if (lds <= (size_t)kLdsSixth && a.max_groups == 0)
-      kern = k_median_tiered<T, ADAPT, D3, 6>;
-    else if (lds <= (size_t)kLdsQuarter && a.max_groups == 0)
-      kern = k_median_tiered<T, ADAPT, D3, 4>;
-    else if (lds <= (size_t)kLdsThird)
-      kern = k_median_tiered<T, ADAPT, D3, 3>;
-  }
+  // the register cap that lets the LDS budget's workgroups share a CU (both
+  // trees: adaptive 16-bit volumes at r = 1 26.9 -> 14.4 ms with the uniform
+  // tree's tiles, 8-bit 8192^2 r = 64 7.8 -> 6.6 ms)
+  if (lds <= (size_t)kLdsSixth && a.max_groups == 0)
+    kern = k_median_tiered<T, ADAPT, D3, 6>;
+  else if (lds <= (size_t)kLdsQuarter && a.max_groups == 0)
+    kern = k_median_tiered<T, ADAPT, D3, 4>;
+  else if (lds <= (size_t)kLdsThird)
+    kern = k_median_tiered<T, ADAPT, D3, 3>;
   hipError_t e = ensure_dynamic_lds((const void*)kern, lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (int64_t)a.strips * a.segs * a.d;
@@ -1555,7 +1556,10 @@ hipError_t prime_type() {
       (const void*)k_median_tiered<T, false, false, 4>, (const void*)k_median_tiered<T, false, false, 6>,
       (const void*)k_median_tiered<T, false, true, 1>,  (const void*)k_median_tiered<T, false, true, 3>,
       (const void*)k_median_tiered<T, false, true, 4>,  (const void*)k_median_tiered<T, false, true, 6>,
-      (const void*)k_median_tiered<T, true, false, 1>,  (const void*)k_median_tiered<T, true, true, 1>,
+      (const void*)k_median_tiered<T, true, false, 1>,  (const void*)k_median_tiered<T, true, false, 3>,
+      (const void*)k_median_tiered<T, true, false, 4>,  (const void*)k_median_tiered<T, true, false, 6>,
+      (const void*)k_median_tiered<T, true, true, 1>,   (const void*)k_median_tiered<T, true, true, 3>,
+      (const void*)k_median_tiered<T, true, true, 4>,   (const void*)k_median_tiered<T, true, true, 6>,
       (const void*)k_median_tiered<T, false, false, 1, true>,
       (const void*)k_median_tiered<T, false, false, 3, true>};
   for (const void* k : ks) {
