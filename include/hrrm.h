@@ -230,11 +230,13 @@ int32_t hrrm_batch_capacity(void);
  *                tier's slot; each wave holds its own slots of deeper subtrees
  *                for the 64 + 2r + 1 columns its windows cover (nslots then
  *                caps the slots per wave); 0 = every slot shared
- *   window_rows: > 0 = (2-D, full precision) the grey-level-window kernel:
- *                each wave holds the leaves of 128 consecutive grey levels
- *                per column of a 64-column strip and skips the tree levels
- *                above them (Sec. III; adaptive: placed on the medians,
- *                Sec. III-C), strip segments of window_rows rows; the rows a
+ *   window_rows: > 0 = (2-D full precision, and 16-bit volumes) the
+ *                grey-level-window kernel: each wave holds the leaves of 128
+ *                (16-bit 2-D r <= 7: 256) consecutive grey levels per column
+ *                of a 64-column strip (a volume's column: its rows and
+ *                slices) and skips the tree levels above them (Sec. III;
+ *                adaptive: placed on the medians, Sec. III-C), strip
+ *                segments of window_rows rows; the rows a
  *                strip cannot finish (byte overflow of a leaf count, medians
  *                spread wider than the scanned leaves) are recomputed by the
  *                tiered kernel with the uniform tree's default configuration.

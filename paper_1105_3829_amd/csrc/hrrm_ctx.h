@@ -83,9 +83,11 @@ int run_batched(Context* ctx, const hrrm_image* images, int count, hipStream_t s
 // alone: the image has the GPU to itself (segments shortened until it fills
 // the GPU, and the launch's last generation of waves in half-height
 // segments); in a batch the other images fill it
+// (volumes: d slices of slice strides sss / dss, cube windows)
 int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, int bytes,
                  int64_t w, int64_t h, int64_t srs, int64_t drs, int r, int64_t rank,
-                 bool adaptive, WindowArgs& wa, MedianArgs& fa, bool alone);
+                 bool adaptive, WindowArgs& wa, MedianArgs& fa, bool alone, int dims = 2,
+                 int64_t d = 1, int64_t sss = 0, int64_t dss = 0);
 // est / est_rs: optional estimate image for the adaptive topology (2-D)
 int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, int64_t h,
                int64_t d, int64_t srs, int64_t sss, int64_t drs, int64_t dss, int r,

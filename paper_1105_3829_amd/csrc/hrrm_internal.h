@@ -109,8 +109,10 @@ struct WindowArgs {
   const void* src;
   void* dst;
   int64_t w, h, srs, drs;
+  int64_t d, sss, dss;  // volumes: slices and slice strides (images: d = 1)
   int64_t rank;
-  int32_t r, n;  // radius, window size (2r+1)^2
+  int32_t r, n;  // radius, window size (2r+1)^dims
+  int32_t dims;  // 2, or 3: cube windows, tiles of every slice
   int32_t seg_rows, strips, segs;
   // Tiles near the image's edges, whose windows are dominated by a repeated
   // edge column or row (so that their medians stray from their neighbours'),
@@ -125,7 +127,7 @@ struct WindowArgs {
   int32_t wave_bytes;  // LDS bytes of one wave
   int32_t bq;          // dwords of leaf counters per column: 32 or 64 (uniform tree)
   uint32_t* need;
-  int32_t fb_strips, fb_rows;
+  int32_t fb_strips, fb_rows, fb_segs;
 };
 
 // One image of a multi-image window launch: its arguments and the exclusive

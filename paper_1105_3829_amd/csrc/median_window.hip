@@ -262,23 +262,26 @@ __device__ __forceinline__ int descend(vu<SQ> W, int kp, int win, bool& ok) {
 // Exact rank-K value of the clamp-to-edge window of pixel (xc, yc), by two
 // 256-bin histograms (high byte, then low byte among values with that high
 // byte; 8-bit data: one).  hist: 256 dwords of the wave's LDS.
-template <typename T>
+template <typename T, bool D3>
 __device__ __forceinline__ int window_rank_exact(const T* __restrict__ src, int64_t srs, int64_t w, int64_t h,
                                  int64_t xc, int64_t yc, int r, int rank, uint32_t* hist,
-                                 int lane) {
+                                 int lane, int64_t sss, int64_t d, int64_t zc) {
+  const int zr = D3 ? r : 0;
   constexpr int kPasses = sizeof(T) == 2 ? 2 : 1;
   constexpr int kB = 32;  // window rows loaded before any is counted
   int k = rank, prefix = 0;
   for (int pass = 0; pass < kPasses; ++pass) {
     *(uint4*)(hist + 4 * lane) = make_uint4(0u, 0u, 0u, 0u);
     __builtin_amdgcn_wave_barrier();
+    for (int dz = -zr; dz <= zr; ++dz)
     for (int dx0 = -r; dx0 <= r; dx0 += 64) {
+      const T* sz = D3 ? src + clampi(zc + dz, d - 1) * sss : src;
       const int dx = dx0 + lane;
       const int64_t col = clampi(xc + dx, w - 1);
       for (int dy0 = -r; dy0 <= r; dy0 += kB) {
         int v[kB];
 #pragma unroll
-        for (int t = 0; t < kB; ++t) v[t] = (int)src[clampi(yc + dy0 + t, h - 1) * srs + col];
+        for (int t = 0; t < kB; ++t) v[t] = (int)sz[clampi(yc + dy0 + t, h - 1) * srs + col];
 #pragma unroll
         for (int t = 0; t < kB; ++t) {
           if (dx <= r && dy0 + t <= r) {
@@ -324,14 +327,16 @@ __device__ __forceinline__ int window_rank_exact(const T* __restrict__ src, int6
 
 
 // Rebuild every held column's counters, and the base, for the window of row
-// y from the raw values: zero, insert the 2r + 1 clamped rows of each column,
-// then base = sum of columns 0..2r.  Values are loaded sixteen rows at a time
-// before any is inserted, so their latencies overlap.
-template <typename T, int KC, int BQ>
+// y from the raw values: zero, insert the 2r + 1 clamped rows of each column
+// (volumes: of each of the 2r + 1 clamped slices around z), then base = sum
+// of columns 0..2r.  Values are loaded sixteen rows at a time before any is
+// inserted, so their latencies overlap.
+template <typename T, int KC, int BQ, bool D3>
 __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, int h, int r,
                                         const int (&gx)[KC], int ncols, const WaveLds& L,
                                         int wave_dwords, int y, int bc, int q0, int sq,
-                                        int lane) {
+                                        int lane, int64_t sss, int64_t d, int64_t zc) {
+  const int zr = D3 ? r : 0;
   using Y = Layout<BQ>;
   uint4* z = (uint4*)L.bins;
   for (int i = lane; i < wave_dwords / 4; i += 64) z[i] = make_uint4(0u, 0u, 0u, 0u);
@@ -340,12 +345,14 @@ __device__ __forceinline__ void rebuild(const T* __restrict__ src, int64_t srs, 
   uint32_t lohi[KC];  // each lane alone updates its columns' lo/hi: kept in registers
 #pragma unroll
   for (int k = 0; k < KC; ++k) lohi[k] = 0u;
+  for (int dz = -zr; dz <= zr; ++dz)
   for (int j0 = -r; j0 <= r; j0 += kBatch) {
+    const T* sz = D3 ? src + clampi(zc + dz, d - 1) * sss : src;
     const T* rows[kBatch];
 #pragma unroll
     for (int t = 0; t < kBatch; ++t) {
       const int yy = y + j0 + t;
-      rows[t] = src + (int64_t)(yy < 0 ? 0 : (yy > h - 1 ? h - 1 : yy)) * srs;
+      rows[t] = sz + (int64_t)(yy < 0 ? 0 : (yy > h - 1 ? h - 1 : yy)) * srs;
     }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -525,17 +532,24 @@ __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2
 
 // One wave's tile `tile` of the image `a` (tiles in launch order: short
 // segments near the image's edges first (see WindowArgs), then the inner
-// strips' segments, neighbouring strips together); wv = the wave's index in
-// its workgroup, uniform (its LDS area).
-template <typename T, bool ADAPT, int KC, int BQ>
+// strips' segments, neighbouring strips together; volumes (D3): every slice
+// of one 2-D tile in turn, so that neighbouring waves read the same rows);
+// wv = the wave's index in its workgroup, uniform (its LDS area).  A volume's
+// column holds the (2r + 1) x (2r + 1) values of its rows and slices.
+template <typename T, bool ADAPT, int KC, int BQ, bool D3 = false>
 __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, int wv,
                                             uint8_t* lds) {
   using Y = Layout<BQ>;
   const int lane = threadIdx.x & 63;
   int strip, y0, y1;
+  int z = 0;
+  if constexpr (D3) {
+    z = (int)(tile % a.d);
+    tile /= a.d;
+  }
   if (!window_tile_rows(a, tile, strip, y0, y1)) return;
   const T* __restrict__ src = (const T*)a.src;
-  T* __restrict__ dst = (T*)a.dst;
+  T* __restrict__ dst = (T*)a.dst + (D3 ? z * a.dss : 0);
   const int r = a.r, r2 = 2 * a.r, ncols = 64 + 2 * a.r;
   const int w = (int)a.w, h = (int)a.h;
   const int x0 = strip * 64;
@@ -586,15 +600,18 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   auto sq = [&]() { return wide ? Y::kBinQ : 16; };
   auto estimate = [&](int lane_of, int y) -> int {
     const int xc = x0 + lane_of < w ? x0 + lane_of : w - 1;
-    return window_rank_exact<T>(src, a.srs, a.w, a.h, xc, y, r, rank, L.bins, lane);
+    return window_rank_exact<T, D3>(src, a.srs, a.w, a.h, xc, y, r, rank, L.bins, lane,
+                                    D3 ? a.sss : 0, D3 ? a.d : 1, z);
   };
   auto build = [&](int y) {
-    rebuild<T, KC, BQ>(src, a.srs, h, r, gx, ncols, L, wave_dwords, y, bc, q0, sq(), lane);
+    rebuild<T, KC, BQ, D3>(src, a.srs, h, r, gx, ncols, L, wave_dwords, y, bc, q0, sq(), lane,
+                           D3 ? a.sss : 0, D3 ? a.d : 1, z);
   };
   // a row this strip cannot finish: flag the tiered kernel's tile holding it
   // (that tile is recomputed whole after this launch)
   auto flag_row = [&](int y) {
-    if (lane == 0) a.need[(int64_t)(y / a.fb_rows) * a.fb_strips + x0 / kBlock] = 1u;
+    const int64_t seg = (D3 ? (int64_t)z * a.fb_segs : 0) + y / a.fb_rows;
+    if (lane == 0) a.need[seg * a.fb_strips + x0 / kBlock] = 1u;
   };
 
   place(estimate(32, y0));
@@ -602,11 +619,12 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   int prev = -1;  // this lane's result in the previous row
 
   for (int y = y0; y < y1; ++y) {
-    // raw values of the next row step, loaded before they are needed
+    // raw values of the next row step (rows yo out, yi in), loaded before
+    // they are needed (volumes: at the step, slice by slice)
+    const int yo = y - r < 0 ? 0 : (y - r > h - 1 ? h - 1 : y - r);
+    const int yi = y + r + 1 > h - 1 ? h - 1 : y + r + 1;
     int vo[KC], vi[KC];
-    {
-      const int yo = y - r < 0 ? 0 : (y - r > h - 1 ? h - 1 : y - r);
-      const int yi = y + r + 1 > h - 1 ? h - 1 : y + r + 1;
+    if constexpr (!D3) {
       const T* ro = src + (int64_t)yo * a.srs;
       const T* ri = src + (int64_t)yi * a.srs;
 #pragma unroll
@@ -767,6 +785,17 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     // row step y -> y + 1: remove row y - r, insert row y + r + 1 (clamped);
     // a removal and an insertion in one dword are one update
     const int s = sq();
+    for (int dz = D3 ? -r : 0; dz <= (D3 ? r : 0); ++dz) {
+    if constexpr (D3) {
+      const T* sz = src + clampi(z + dz, a.d - 1) * a.sss;
+      const T* ro = sz + (int64_t)yo * a.srs;
+      const T* ri = sz + (int64_t)yi * a.srs;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        vo[k] = (int)ro[gx[k]];
+        vi[k] = (int)ri[gx[k]];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
       const int c = lane + 64 * k;
@@ -787,6 +816,7 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
         }
       }
     }
+    }
     __builtin_amdgcn_wave_barrier();
   }
 }
@@ -794,13 +824,13 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
 // Columns one lane holds: ceil((64 + 2r) / 64).
 constexpr int kc_for(int r) { return (64 + 2 * r + 63) / 64; }
 
-template <typename T, bool ADAPT, int KC, int WPG, int BQ>
+template <typename T, bool ADAPT, int KC, int WPG, int BQ, bool D3 = false>
 __global__ __launch_bounds__(64 * WPG) void k_median_window(WindowArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   // the wave's index in the workgroup, as a value the compiler knows to be
   // uniform: everything derived from it (tile, rows, range) stays scalar
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  window_tile<T, ADAPT, KC, BQ>(a, (int64_t)blockIdx.x * WPG + wv, wv, lds);
+  window_tile<T, ADAPT, KC, BQ, D3>(a, (int64_t)blockIdx.x * WPG + wv, wv, lds);
 }
 
 // Many images in one launch (uniform tree): workgroup g belongs to the first
@@ -826,14 +856,14 @@ __global__ __launch_bounds__(64 * WPG) void k_median_window_multi(
   window_tile<T, false, KC, 32>(a, (g - first) * WPG + wv, wv, lds);
 }
 
-template <typename T, bool ADAPT, int KC, int WPG, int BQ = 32>
+template <typename T, bool ADAPT, int KC, int WPG, int BQ = 32, bool D3 = false>
 hipError_t launch_k(const WindowArgs& a, hipStream_t stream) {
   const size_t lds = (size_t)WPG * a.wave_bytes;
-  const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG, BQ>;
+  const void* kern = (const void*)k_median_window<T, ADAPT, KC, WPG, BQ, D3>;
   hipError_t e = ensure_dynamic_lds(kern, lds);
   if (e != hipSuccess) return e;
   const int64_t grid = (window_tiles(a) + WPG - 1) / WPG;
-  hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG, BQ>), dim3((uint32_t)grid),
+  hipLaunchKernelGGL((k_median_window<T, ADAPT, KC, WPG, BQ, D3>), dim3((uint32_t)grid),
                      dim3(64 * WPG), lds, stream, a);
   return hipGetLastError();
 }
@@ -869,12 +899,16 @@ hipError_t prime_w() {
     const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
     if (e != hipSuccess) return e;
   }
+  if constexpr (sizeof(T) == 2)
+    return ensure_dynamic_lds((const void*)k_median_window<T, ADAPT, 2, 1, 32, true>, kLdsLimit);
   return hipSuccess;
 }
 
 }  // namespace
 
-int64_t window_tiles(const WindowArgs& a) { return window_tile_count(a); }
+int64_t window_tiles(const WindowArgs& a) {
+  return window_tile_count(a) * (a.dims == 3 ? a.d : 1);
+}
 
 // Waves per CU with workgroups of wpg waves at radius r (LDS is granted to a
 // workgroup in blocks of 1,280 bytes).
@@ -947,6 +981,14 @@ int window_waves_per_group(int r) {
 }
 
 hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStream_t stream) {
+  if (a.dims == 3) {
+    // 16-bit volumes, r <= 7: two columns per lane, 128 grey levels, one-wave
+    // workgroups (14 waves per CU at r = 7)
+    if (bytes != 2 || a.bq != 32 || kc_for(a.r) != 2 || window_launch_wpg(2, a.r, 32) != 1)
+      return hipErrorInvalidValue;
+    return adaptive ? launch_k<uint16_t, true, 2, 1, 32, true>(a, stream)
+                    : launch_k<uint16_t, false, 2, 1, 32, true>(a, stream);
+  }
   if (bytes == 1)
     return adaptive ? launch_w<uint8_t, true>(a, stream) : launch_w<uint8_t, false>(a, stream);
   return adaptive ? launch_w<uint16_t, true>(a, stream) : launch_w<uint16_t, false>(a, stream);
