@@ -433,7 +433,7 @@ int run_filter(Context* ctx, const void* src, void* dst, int dtype, int64_t w, i
   if (dims == 2 && drop == 0 && !full && est == nullptr && t.window_rows > 0)
     return run_window(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, adaptive, stream,
                       nullptr);
-  if (dims == 3 && bytes == 2 && !full && t.window_rows > 0)
+  if (dims == 3 && bytes == 2 && !full && t.window_rows > 0 && r >= 1)
     return run_window(ctx, t, src, dst, bytes, w, h, srs, drs, r, rank, adaptive, stream,
                       nullptr, 3, d, sss, dss);
 

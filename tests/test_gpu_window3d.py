@@ -115,3 +115,19 @@ def test_default_tiles(hrrm, ctx, variant):
     vol = datagen.xray_volume_u16(10, 60, 140, seed=45)
     _check(hrrm, ctx, "xray", vol, 3, variant, None)
     _check(hrrm, ctx, "xray", vol, 2, variant, None)
+
+
+def test_forced_tiles_outside_the_window_path(hrrm, ctx):
+    # window_rows > 0 where the window kernel does not serve volumes (r = 0,
+    # 8-bit data): the tiered kernel computes them, with the same results
+    vol = datagen.xray_volume_u16(4, 20, 70, seed=46)
+    _check(hrrm, ctx, "xray", vol, 0, "plain", 32)
+    v8 = datagen.rng(47).integers(0, 256, size=(5, 20, 70), dtype=np.uint8)
+    announce("window3d", "u8 forced", v8.shape)
+    ctx.set_tile(hrrm.U8, 3, 2, "plain", window_rows=32)
+    try:
+        got = to_host(ctx.median3d(to_dev(v8), 2))
+    finally:
+        ctx.set_tile(hrrm.U8, 3, 2, "plain")
+    want = oracle.median3d(v8, 2)
+    assert np.array_equal(got, want), first_mismatch(got, want)
