@@ -199,13 +199,13 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
   if (dims == 2 && r >= 1 &&
       (bytes == 1 ? r <= (adaptive ? 32 : 24) : (adaptive || r >= 4)))
     t.window_rows = r <= 24 ? 32 : 64;  // C1 r = 15: 0.41 adaptive, 0.49 ms plain
-  // 16-bit volumes: the window kernel over every slice (X-ray-like
-  // 512 x 512 x 256 with 1 % impulses, 32-row segments; uniform tree r = 3
-  // 9.9 against 14.6 ms, r = 5 6.9 against 17.1, r = 7 7.8 against 22.5;
-  // adaptive from r = 2: 21.8 against 32.2, r = 5 6.4 against 166; at r = 1
-  // and (uniform) r = 2 the medians of 27- and 125-value cubes spread wider
-  // than a pass covers: 32.6 against 5.4, 17.3 against 12.3)
-  if (dims == 3 && bytes == 2 && r >= (adaptive ? 2 : 3)) t.window_rows = 32;
+  // 16-bit volumes from r = 2: the window kernel over every slice
+  // (X-ray-like 512 x 512 x 256 with 1 % impulses, 256 grey levels per
+  // column up to r = 3; uniform tree r = 2 7.2 against 12.3 ms, r = 3 6.0
+  // against 14.6, r = 5 6.4 against 17.1, r = 7 7.8 against 22.5; adaptive
+  // r = 2 7.9 against 32.2, r = 5 6.1 against 166); at r = 1 the medians of
+  // 27-value cubes spread wider than a pass covers (40 against 5.4 ms)
+  if (dims == 3 && bytes == 2 && r >= 2) t.window_rows = r <= 2 ? 16 : 32;
   // an image filtered on its own keeps at least two tiles per workgroup slot
   // of the GPU (256 CUs, 1 to 6 workgroups each) when it allows it; in a
   // batch the other images fill the GPU
@@ -376,7 +376,10 @@ int window_setup(Context* ctx, const TileConfig& t, const void* src, void* dst, 
   wa.n = dims == 3 ? span * span * span : span * span;
   // waves the GPU holds at once (segment sizing of an image launched alone;
   // a volume's slices give every launch tiles enough)
-  wa.bq = dims == 3 ? 32 : window_bq(bytes, r, adaptive);
+  // (volumes: 256 grey levels up to r = 3, r = 3 9.3 -> 6.0 ms; from r = 4
+  // the 128-level columns' occupancy wins, r = 4 6.5 against 7.2, r = 5 6.4
+  // against 9.6)
+  wa.bq = dims == 3 ? (r <= 3 ? 64 : 32) : window_bq(bytes, r, adaptive);
   const int64_t slots = (int64_t)ctx->cu_count() * window_waves_per_cu(bytes, r, wa.bq);
   window_geometry(wa, w, h, t.window_rows, slots, alone && dims == 2, r);
   wa.wave_bytes = (int32_t)window_wave_bytes(r, wa.bq);

@@ -901,8 +901,12 @@ hipError_t prime_w() {
     const hipError_t e = ensure_dynamic_lds(k, kLdsLimit);
     if (e != hipSuccess) return e;
   }
-  if constexpr (sizeof(T) == 2)
-    return ensure_dynamic_lds((const void*)k_median_window<T, ADAPT, 2, 1, 32, true>, kLdsLimit);
+  if constexpr (sizeof(T) == 2) {
+    const hipError_t e =
+        ensure_dynamic_lds((const void*)k_median_window<T, ADAPT, 2, 1, 32, true>, kLdsLimit);
+    if (e != hipSuccess) return e;
+    return ensure_dynamic_lds((const void*)k_median_window<T, ADAPT, 2, 1, 64, true>, kLdsLimit);
+  }
   return hipSuccess;
 }
 
@@ -984,10 +988,14 @@ int window_waves_per_group(int r) {
 
 hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStream_t stream) {
   if (a.dims == 3) {
-    // 16-bit volumes, r <= 7: two columns per lane, 128 grey levels, one-wave
-    // workgroups (14 waves per CU at r = 7)
-    if (bytes != 2 || a.bq != 32 || kc_for(a.r) != 2 || window_launch_wpg(2, a.r, 32) != 1)
+    // 16-bit volumes, r <= 7: two columns per lane, 128 grey levels (r <= 2:
+    // 256), one-wave workgroups (14 waves per CU at r = 7)
+    if (bytes != 2 || kc_for(a.r) > 2 || window_launch_wpg(2, a.r, a.bq) != 1)
       return hipErrorInvalidValue;
+    if (a.bq == 64)
+      return adaptive ? launch_k<uint16_t, true, 2, 1, 64, true>(a, stream)
+                      : launch_k<uint16_t, false, 2, 1, 64, true>(a, stream);
+    if (a.bq != 32) return hipErrorInvalidValue;
     return adaptive ? launch_k<uint16_t, true, 2, 1, 32, true>(a, stream)
                     : launch_k<uint16_t, false, 2, 1, 32, true>(a, stream);
   }

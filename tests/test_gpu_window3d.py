@@ -62,6 +62,7 @@ def test_xray_volume(hrrm, ctx, r, variant):
 def test_segment_heights(hrrm, ctx, window_rows):
     vol = datagen.xray_volume_u16(9, 40, 131, seed=41)
     _check(hrrm, ctx, "xray", vol, 3, "plain", window_rows)
+    _check(hrrm, ctx, "xray", vol, 4, "adaptive", window_rows)
 
 
 @pytest.mark.parametrize("variant", ["plain", "adaptive"])
@@ -69,6 +70,7 @@ def test_rows_left_to_the_tiered_kernel(hrrm, ctx, variant):
     # full-range noise: rows whose medians no pass holds go to the tiered
     # kernel's 3-D pass, whose flags carry the slice
     _check(hrrm, ctx, "noise", _noise(7, 50, 140, seed=42), 3, variant, 16)
+    _check(hrrm, ctx, "noise", _noise(6, 40, 130, seed=48), 5, variant, 16)
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 5, 70), (3, 1, 1), (2, 9, 65), (5, 33, 129),
@@ -110,11 +112,11 @@ def test_strided_volume(hrrm, ctx):
 
 @pytest.mark.parametrize("variant", ["plain", "adaptive"])
 def test_default_tiles(hrrm, ctx, variant):
-    # the defaults send 16-bit volumes from r = 3 (adaptive: 2) to the window
-    # kernel
+    # the defaults send 16-bit volumes from r = 2 to the window kernel (256
+    # grey levels per column up to r = 3)
     vol = datagen.xray_volume_u16(10, 60, 140, seed=45)
-    _check(hrrm, ctx, "xray", vol, 3, variant, None)
-    _check(hrrm, ctx, "xray", vol, 2, variant, None)
+    for r in (1, 2, 3, 4):
+        _check(hrrm, ctx, "xray", vol, r, variant, None)
 
 
 def test_forced_tiles_outside_the_window_path(hrrm, ctx):
