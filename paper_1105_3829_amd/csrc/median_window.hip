@@ -622,19 +622,22 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
 
   for (int y = y0; y < y1; ++y) {
     // raw values of the next row step (rows yo out, yi in), loaded before
-    // they are needed (volumes: at the step, slice by slice)
+    // they are needed (volumes: those of its first slice; each further
+    // slice's are loaded while the one before is applied)
     const int yo = y - r < 0 ? 0 : (y - r > h - 1 ? h - 1 : y - r);
     const int yi = y + r + 1 > h - 1 ? h - 1 : y + r + 1;
     int vo[KC], vi[KC];
-    if constexpr (!D3) {
-      const T* ro = src + (int64_t)yo * a.srs;
-      const T* ri = src + (int64_t)yi * a.srs;
+    auto load_slice = [&](int zz, int (&o)[KC], int (&i)[KC]) {
+      const T* sz = src + (D3 ? clampi(zz, a.d - 1) * a.sss : 0);
+      const T* ro = sz + (int64_t)yo * a.srs;
+      const T* ri = sz + (int64_t)yi * a.srs;
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
-        vo[k] = (int)ro[gx[k]];
-        vi[k] = (int)ri[gx[k]];
+        o[k] = (int)ro[gx[k]];
+        i[k] = (int)ri[gx[k]];
       }
-    }
+    };
+    load_slice(z - r, vo, vi);
     // passes over the row until every live pixel has its result: a range
     // that misses some medians moves (adaptive: first to all 128 leaves;
     // uniform: by one subtree) or is rebuilt around the exact median of the
@@ -788,16 +791,8 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
     // a removal and an insertion in one dword are one update
     const int s = sq();
     for (int dz = D3 ? -r : 0; dz <= (D3 ? r : 0); ++dz) {
-    if constexpr (D3) {
-      const T* sz = src + clampi(z + dz, a.d - 1) * a.sss;
-      const T* ro = sz + (int64_t)yo * a.srs;
-      const T* ri = sz + (int64_t)yi * a.srs;
-#pragma unroll
-      for (int k = 0; k < KC; ++k) {
-        vo[k] = (int)ro[gx[k]];
-        vi[k] = (int)ri[gx[k]];
-      }
-    }
+    int no[KC], ni[KC];
+    if (D3 && dz < r) load_slice(z + dz + 1, no, ni);
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
       const int c = lane + 64 * k;
@@ -816,6 +811,13 @@ __device__ __forceinline__ void window_tile(const WindowArgs& a, int64_t tile, i
           lds_add(L.base + (same ? Y::kSink : o.q), same ? 0u : 0u - o.inc);
           lds_add(L.base + Y::kLohi, dl);
         }
+      }
+    }
+    if (D3 && dz < r) {
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        vo[k] = no[k];
+        vi[k] = ni[k];
       }
     }
     }
