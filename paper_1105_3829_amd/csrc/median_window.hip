@@ -990,7 +990,7 @@ int window_waves_per_group(int r) {
 
 hipError_t launch_window(const WindowArgs& a, int bytes, bool adaptive, hipStream_t stream) {
   if (a.dims == 3) {
-    // 16-bit volumes, r <= 7: two columns per lane, 128 grey levels (r <= 2:
+    // 16-bit volumes, r <= 7: two columns per lane, 128 grey levels (r <= 3:
     // 256), one-wave workgroups (14 waves per CU at r = 7)
     if (bytes != 2 || kc_for(a.r) > 2 || window_launch_wpg(2, a.r, a.bq) != 1)
       return hipErrorInvalidValue;
