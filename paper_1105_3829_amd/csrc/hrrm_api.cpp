@@ -202,10 +202,11 @@ TileConfig default_tile(int bytes, int dims, int r, bool adaptive, int64_t w, in
     // 64, r = 10 0.54 against 0.55); longer ones share each build among more
     // rows where a build reads 2r + 1 rows (C1 r = 31 at 64 rows against 32:
     // 0.59 -> 0.57 ms, adaptive 0.49 -> 0.45; r = 50 at 128 against 64:
-    // 1.16 -> 1.13, r = 100 2.70 -> 2.50) and for 8-bit windows from r = 4
-    // (low-key 8192^2 at 64 rows against 32: r = 4 0.78 -> 0.76 ms, r = 8
-    // 0.84 -> 0.80, r = 16 1.08 -> 0.99, r = 24 1.24 -> 1.11)
-    t.window_rows = r > 40 ? 128 : (r > 16 || (bytes == 1 && r >= 4)) ? 64 : 32;
+    // 1.16 -> 1.13, r = 100 2.70 -> 2.50) and for 8-bit windows (low-key
+    // 8192^2 at 64 rows against 32: r = 1 1.01 -> 0.99 ms, r = 2 0.78 ->
+    // 0.74, r = 4 0.78 -> 0.76, r = 8 0.84 -> 0.80, r = 16 1.08 -> 0.99,
+    // r = 24 1.24 -> 1.11)
+    t.window_rows = r > 40 ? 128 : (r > 16 || bytes == 1) ? 64 : 32;
   // 16-bit volumes from r = 2: the window kernel over every slice
   // (X-ray-like 512 x 512 x 256 with 1 % impulses, 256 grey levels per
   // column up to r = 3; uniform tree r = 2 7.2 against 12.3 ms, r = 3 6.0
